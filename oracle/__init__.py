@@ -1,0 +1,115 @@
+"""CPU FP64 oracle for the Hawkes log-likelihood and gradient.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of the benchmark.  The product path never imports it.
+
+`build()` compiles oracle.c twice: single-threaded (the oracle proper) and
+with OpenMP over rows (bitwise-identical results, used only to time the oracle
+on all host cores and to evaluate full-size cases in tests).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB1 = os.path.join(HERE, "liboracle.so")
+LIBMT = os.path.join(HERE, "liboracle_omp.so")
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11"]
+
+ZERORATE = -4
+
+
+def build(force: bool = True) -> None:
+    for out, extra in ((LIB1, []), (LIBMT, ["-fopenmp"])):
+        if force or not os.path.exists(out):
+            subprocess.check_call(["gcc", *CFLAGS, *extra, SRC, "-o", out, "-lm"])
+
+
+_libs: dict = {}
+
+
+def _lib(threads: bool):
+    key = bool(threads)
+    if key not in _libs:
+        path = LIBMT if threads else LIB1
+        if not os.path.exists(path):
+            build(force=False)
+        lib = ctypes.CDLL(path)
+        d = ctypes.POINTER(ctypes.c_double)
+        i64 = ctypes.c_int64
+        lib.oracle_loglik_grad.argtypes = [d, d, i64, ctypes.c_int, d, d, d, d]
+        lib.oracle_rates.argtypes = [d, d, i64, ctypes.c_int, d, d, d]
+        lib.oracle_grad_rows.argtypes = [d, d, i64, ctypes.c_int, d, d, ctypes.POINTER(i64), i64, d]
+        lib.oracle_diagnostics.argtypes = [d, d, i64, ctypes.c_int, d, ctypes.c_double, d, ctypes.POINTER(i64)]
+        for f in (lib.oracle_loglik_grad, lib.oracle_rates, lib.oracle_grad_rows, lib.oracle_diagnostics):
+            f.restype = ctypes.c_int
+        _libs[key] = lib
+    return _libs[key]
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+def _prep(x, t, params):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    assert x.shape[0] == t.shape[0] and p.shape == (6,)
+    return x, t, p
+
+
+def loglik_grad(x, t, params, threads: bool = False, want_grad_x: bool = True):
+    """Returns (status, ll, grad_x (N,D) or None, grad_params (6,))."""
+    x, t, p = _prep(x, t, params)
+    n, d = x.shape
+    ll = np.zeros(1)
+    gx = np.zeros((n, d)) if want_grad_x else None
+    gp = np.zeros(6)
+    st = _lib(threads).oracle_loglik_grad(_p(x), _p(t), n, d, _p(p), _p(ll), _p(gx), _p(gp))
+    return st, float(ll[0]), gx, gp
+
+
+def rates(x, t, params, threads: bool = False):
+    """Returns (lambda (N,), row sums (N,6) = K,R,U,J,V,W unweighted)."""
+    x, t, p = _prep(x, t, params)
+    n, d = x.shape
+    lam = np.zeros(n)
+    s6 = np.zeros((n, 6))
+    st = _lib(threads).oracle_rates(_p(x), _p(t), n, d, _p(p), _p(lam), _p(s6))
+    if st != 0:
+        raise ValueError(f"oracle_rates status {st}")
+    return lam, s6
+
+
+def grad_rows(x, t, params, lam, rows, threads: bool = True):
+    x, t, p = _prep(x, t, params)
+    n, d = x.shape
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    out = np.zeros((rows.shape[0], d))
+    st = _lib(threads).oracle_grad_rows(_p(x), _p(t), n, d, _p(p), _p(lam),
+                                        rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        rows.shape[0], _p(out))
+    if st != 0:
+        raise ValueError(f"oracle_grad_rows status {st}")
+    return out
+
+
+def diagnostics(x, t, params, log_floor=float(np.log(np.finfo(np.float32).tiny)), threads: bool = True):
+    x, t, p = _prep(x, t, params)
+    n, d = x.shape
+    mn = np.zeros(1)
+    cnt = np.zeros(1, dtype=np.int64)
+    st = _lib(threads).oracle_diagnostics(_p(x), _p(t), n, d, _p(p), ctypes.c_double(log_floor), _p(mn),
+                                          cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if st != 0:
+        raise ValueError(f"oracle_diagnostics status {st}")
+    return float(mn[0]), int(cnt[0])
