@@ -1,0 +1,174 @@
+#!/usr/bin/env python
+"""Benchmark: spatiotemporal Hawkes log-likelihood + full gradient on one MI355X.
+
+Workload: the wildfire-like coarsened case, N = 50,000 events in D = 2 (500 km
+box, ten years, 30 % of locations latent in discs), synthetic and seeded.  One
+step is one complete evaluation through the C ABI (hawkes_grad): validation,
+packing, the rate pass, finalize (log-likelihood and the six parameter
+gradients, delivered to the host) and the gradient pass (N x D location
+gradient in device memory).  Inputs are resident in HBM before timing starts.
+
+Throughput is ordered pair-interactions per second, N (N - 1) per step.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair-interactions/s for Hawkes loglik+grad (FP64 vs mixed); serve p50/p99 ms"
+STAGES = ["prep", "pack", "pass1", "reduce1", "flaglist", "fix1", "final1", "final2", "pass2", "fix2b", "fix2a",
+          "reduce2"]
+KERNEL_NAMES = {"pass1": "k_pass1", "pass2": "k_pass2"}
+
+# Peaks of the chip (256 CUs at 2.4 GHz).  FP32 vector: 157.3 TFLOP/s.  The
+# v_exp_f32 issue rate is 32 lanes per CU per clock (measured by the peaks
+# microbenchmark), so one exp occupies the issue time of 8 FP32 FLOPs.
+PEAK_FP32 = 157.3e12
+PEAK_FP64 = 78.6e12
+EXP_F32_PER_S = 256 * 2.4e9 * 32
+FLOP_EQ_PER_EXP = PEAK_FP32 / EXP_F32_PER_S
+
+
+def pass_work(d: int, which: str):
+    """Algorithmic work per unordered pair: (FLOPs with FMA = 2, exps).
+    Rate pass: differences (D+1), r^2 (2D-1), dt^2 (1), two exponents (8),
+    nine accumulations (15).  Gradient pass: recompute (3D+9), weights (6),
+    two-sided scatter (4D)."""
+    return (3 * d + 24, 2) if which == "pass1" else (7 * d + 15, 2)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=50000)
+    ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the sharded design is described "
+              "in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2010_02994_amd import _lib, api, workloads
+
+    dev = torch.device("cuda:0")
+    w = workloads.config2(n=args.n)
+    n, d = w.n, w.d
+    x = torch.tensor(w.x, device=dev)
+    t = torch.tensor(w.t, device=dev)
+    gx = torch.empty_like(x)
+    L = _lib.lib()
+    L.hawkes_grad_timed.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                    ctypes.POINTER(_lib.HawkesParams), ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)]
+    L.hawkes_grad_timed.restype = ctypes.c_int
+    ps = api.params_struct(w.params)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def run(prec: str, steps: int, warmup: int):
+        pc = api._prec(prec)
+        ws = api.workspace(n, d, prec, dev)
+        ll = ctypes.c_double()
+        gp = (ctypes.c_double * 6)()
+        stage = (ctypes.c_float * 12)()
+        for _ in range(warmup):
+            st = L.hawkes_grad_timed(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), pc, ws.data_ptr(),
+                                     ws.numel(), stream, ctypes.byref(ll), gx.data_ptr(), gp, stage)
+            assert st == 0, _lib.strerror(st)
+        torch.cuda.synchronize()
+        acc = np.zeros(12)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = L.hawkes_grad_timed(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), pc, ws.data_ptr(),
+                                     ws.numel(), stream, ctypes.byref(ll), gx.data_ptr(), gp, stage)
+            assert st == 0, _lib.strerror(st)
+            acc += np.array(stage[:])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        return el / steps, acc / steps, ll.value
+
+    sec_mixed, stage_ms, ll_m = run(args.prec, args.steps, args.warmup)
+    pairs = n * (n - 1)
+    value = pairs / sec_mixed
+
+    fp64 = None
+    if args.prec == "mixed" and args.fp64_steps > 0:
+        sec64, stage64, ll_64 = run("fp64", args.fp64_steps, 1)
+        fp64 = {"value": pairs / sec64, "ms_per_step": sec64 * 1e3,
+                "stage_ms": {k: round(float(v), 4) for k, v in zip(STAGES, stage64)},
+                "loglik_rel_diff_mixed_vs_fp64": abs(ll_m - ll_64) / abs(ll_64)}
+
+    # dominant kernel and its roofline (algorithmic work per launch / measured duration)
+    pass_ms = {k: float(stage_ms[STAGES.index(k)]) for k in ("pass1", "pass2")}
+    dom = max(pass_ms, key=pass_ms.get)
+    flops, exps = pass_work(d, dom)
+    pairs_u = n * (n - 1) / 2
+    work = pairs_u * (flops + exps * FLOP_EQ_PER_EXP)
+    achieved = work / (pass_ms[dom] * 1e-3)
+    peak = PEAK_FP32 if args.prec == "mixed" else PEAK_FP64
+    roof = {"bound": "alu", "kernel": f"{KERNEL_NAMES[dom]}<D={d},{args.prec}>",
+            "achieved": round(achieved / 1e12, 3), "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "work_per_unordered_pair": {"flops": flops, "exps": exps, "flop_eq_per_exp": FLOP_EQ_PER_EXP},
+            "kernel_ms": round(pass_ms[dom], 4)}
+    # whole-path roofline: both passes' algorithmic work over the full step time
+    f1, e1 = pass_work(d, "pass1")
+    f2, e2 = pass_work(d, "pass2")
+    path_work = pairs_u * (f1 + f2 + (e1 + e2) * FLOP_EQ_PER_EXP)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_seconds)
+
+    out = {"metric": METRIC, "value": value, "unit": "pair-interactions/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": sec_mixed * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32-pairs/f64-accumulate" if args.prec == "mixed" else "f64",
+           "data": "synthetic",
+           "config": {"workload": w.name, "n_events": n, "d": d, "precision": args.prec,
+                      "pairs_per_step": pairs, "parallelism": "single-gpu"},
+           "roofline": roof,
+           "path_roofline_frac": round(path_work / sec_mixed / peak, 4),
+           "stage_ms": {k: round(float(v), 4) for k, v in zip(STAGES, stage_ms)},
+           "fp64": fp64,
+           "speedup_mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, seconds: float):
+    """The oracle as it stands (OpenMP build over rows, all host cores) on the
+    first N_s events of the same workload, N_s sized for about `seconds`."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n0 = 2000
+    t0 = time.perf_counter()
+    oracle.loglik_grad(w.x[:n0], w.t[:n0], w.params, threads=True)
+    dt0 = time.perf_counter() - t0
+    ns = int(min(w.n, max(n0, n0 * (seconds / max(dt0, 1e-3)) ** 0.5)))
+    t0 = time.perf_counter()
+    st, ll, _, _ = oracle.loglik_grad(w.x[:ns], w.t[:ns], w.params, threads=True)
+    el = time.perf_counter() - t0
+    return {"value": ns * (ns - 1) / el, "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle loglik+grad (C, OpenMP rows) on the first {ns} of {w.n} events of {w.name}",
+            "seconds": round(el, 3)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,84 @@
+"""ctypes loader for libhawkes.so (built in-tree).  No fallback: if the shared
+library is missing the import fails with an explicit error."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhawkes.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "hawkes.h")
+
+OK, EINVAL, EPARAM, EDATA, EZERORATE, ENOMEM, EDEVICE, ESTATE, ETIMEOUT, EPENDING = 0, -1, -2, -3, -4, -5, -6, -7, -8, 1
+FP64, MIXED = 0, 1
+
+
+class HawkesParams(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("mu", "h", "tau", "theta", "omega", "xi")]
+
+
+class HawkesError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} (status {status})" if what else strerror(status))
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libhawkes.so not built at {LIB_PATH}; run __graft_entry__.build() "
+                              f"(python -m paper_2010_02994_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, i64, ci = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        pp = ctypes.POINTER(HawkesParams)
+        hd = ctypes.POINTER(ctypes.c_double)
+        L.hawkes_workspace_bytes.argtypes = [i64, ci, ci]
+        L.hawkes_workspace_bytes.restype = ctypes.c_size_t
+        L.hawkes_loglik.argtypes = [dp, dp, i64, ci, pp, ci, vp, ctypes.c_size_t, vp, hd]
+        L.hawkes_grad.argtypes = [dp, dp, i64, ci, pp, ci, vp, ctypes.c_size_t, vp, hd, dp, hd]
+        L.hawkes_grad_async.argtypes = [dp, dp, i64, ci, pp, ci, vp, ctypes.c_size_t, vp, dp, dp]
+        for f in (L.hawkes_loglik, L.hawkes_grad, L.hawkes_grad_async):
+            f.restype = ci
+        L.hawkes_strerror.argtypes = [ci]
+        L.hawkes_strerror.restype = ctypes.c_char_p
+        L.hawkes_version.restype = ctypes.c_char_p
+        _bind_serve(L)
+        _lib = L
+    return _lib
+
+
+def _bind_serve(L):
+    if not hasattr(L, "hawkes_serve_create"):
+        return
+    vp, ci, i64, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+    L.hawkes_serve_create.argtypes = [ctypes.c_size_t, ci, ci, ctypes.POINTER(vp)]
+    L.hawkes_serve_register.argtypes = [vp, vp, i64, ci, ctypes.POINTER(ctypes.c_int32)]
+    L.hawkes_serve_submit.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(HawkesParams), ci, vp,
+                                      ctypes.POINTER(u64)]
+    L.hawkes_serve_poll.argtypes = [vp, u64, vp]
+    L.hawkes_serve_wait.argtypes = [vp, u64, vp, i64]
+    L.hawkes_serve_destroy.argtypes = [vp]
+    L.hawkes_serve_footprint.argtypes = [i64, ci, ci]
+    L.hawkes_serve_footprint.restype = ctypes.c_size_t
+    for f in (L.hawkes_serve_create, L.hawkes_serve_register, L.hawkes_serve_submit, L.hawkes_serve_poll,
+              L.hawkes_serve_wait, L.hawkes_serve_destroy):
+        f.restype = ci
+
+
+def strerror(status: int) -> str:
+    try:
+        return lib().hawkes_strerror(int(status)).decode()
+    except ImportError:
+        return f"status {status}"
+
+
+def declared_symbols() -> list[str]:
+    """Function names declared in include/hawkes.h."""
+    with open(HEADER) as f:
+        txt = f.read()
+    return sorted(set(re.findall(r"\b(hawkes_[a-z_0-9]+)\s*\(", txt)))

@@ -1,0 +1,111 @@
+"""Python binding of the C ABI: argument marshalling only.  Every step of the
+computation runs in the HIP library; torch provides device memory (the
+workspace comes from torch's caching allocator) and the current HIP stream."""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FP64, MIXED, HawkesError, HawkesParams
+
+PRECISIONS = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
+
+
+def _prec(p) -> int:
+    try:
+        return PRECISIONS[p]
+    except KeyError:
+        raise ValueError(f"precision must be 'fp64' or 'mixed', got {p!r}")
+
+
+def params_struct(params: Sequence[float]) -> HawkesParams:
+    p = [float(v) for v in (params.tolist() if hasattr(params, "tolist") else params)]
+    if len(p) != 6:
+        raise ValueError("params must have 6 entries (mu, h, tau, theta, omega, xi)")
+    return HawkesParams(*p)
+
+
+def workspace_bytes(n: int, d: int, prec="mixed") -> int:
+    return int(_lib.lib().hawkes_workspace_bytes(int(n), int(d), _prec(prec)))
+
+
+_ws_cache: dict = {}
+
+
+def workspace(n: int, d: int, prec, device) -> torch.Tensor:
+    need = workspace_bytes(n, d, prec)
+    if need == 0:
+        raise HawkesError(_lib.EINVAL, "workspace size")
+    key = torch.device(device)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=key)
+        _ws_cache[key] = ws
+    return ws
+
+
+def _check_inputs(x: torch.Tensor, t: torch.Tensor):
+    if not (x.is_cuda and t.is_cuda):
+        raise ValueError("x and t must be device tensors")
+    if x.dtype != torch.float64 or t.dtype != torch.float64:
+        raise ValueError("x and t must be float64")
+    if x.dim() != 2 or t.dim() != 1 or x.shape[0] != t.shape[0]:
+        raise ValueError("x must be (N, D) and t (N,)")
+    return x.contiguous(), t.contiguous()
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def loglik(x: torch.Tensor, t: torch.Tensor, params, prec="mixed") -> float:
+    x, t = _check_inputs(x, t)
+    n, d = x.shape
+    ws = workspace(n, d, prec, x.device)
+    ll = ctypes.c_double(0.0)
+    ps = params_struct(params)
+    st = _lib.lib().hawkes_loglik(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), _prec(prec), ws.data_ptr(),
+                                  ws.numel(), _stream_ptr(x.device), ctypes.byref(ll))
+    if st not in (_lib.OK, _lib.EZERORATE):
+        raise HawkesError(st, "hawkes_loglik")
+    return ll.value
+
+
+def grad(x: torch.Tensor, t: torch.Tensor, params, prec="mixed", out: torch.Tensor | None = None,
+         raise_zero_rate: bool = False):
+    """Returns (loglik, grad_x (N, D) float64 device tensor, grad_params numpy (6,))."""
+    x, t = _check_inputs(x, t)
+    n, d = x.shape
+    ws = workspace(n, d, prec, x.device)
+    gx = out if out is not None else torch.empty_like(x)
+    ll = ctypes.c_double(0.0)
+    gp = (ctypes.c_double * 6)()
+    ps = params_struct(params)
+    st = _lib.lib().hawkes_grad(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), _prec(prec), ws.data_ptr(),
+                                ws.numel(), _stream_ptr(x.device), ctypes.byref(ll), gx.data_ptr(), gp)
+    if st != _lib.OK and (st != _lib.EZERORATE or raise_zero_rate):
+        raise HawkesError(st, "hawkes_grad")
+    return ll.value, gx, np.array(gp[:])
+
+
+def grad_async(x: torch.Tensor, t: torch.Tensor, params, prec="mixed", out8: torch.Tensor | None = None,
+               grad_x: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """Enqueue a full evaluation on the current stream without synchronizing.
+    out8 (device, 8 doubles) receives [loglik, 6 parameter gradients, status]."""
+    x, t = _check_inputs(x, t)
+    n, d = x.shape
+    if ws is None:
+        ws = workspace(n, d, prec, x.device)
+    if out8 is None:
+        out8 = torch.empty(8, dtype=torch.float64, device=x.device)
+    ps = params_struct(params)
+    st = _lib.lib().hawkes_grad_async(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), _prec(prec),
+                                      ws.data_ptr(), ws.numel(), _stream_ptr(x.device), out8.data_ptr(),
+                                      grad_x.data_ptr() if grad_x is not None else None)
+    if st != _lib.OK:
+        raise HawkesError(st, "hawkes_grad_async")
+    return out8

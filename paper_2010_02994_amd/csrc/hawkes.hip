@@ -1,0 +1,332 @@
+// libhawkes: C ABI, workspace layout and launch sequence of the gfx950 Hawkes
+// log-likelihood + gradient (arXiv 2010.02994, Sec. 2.1 and App. A).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+
+#include "../../include/hawkes.h"
+#include "hawkes_common.hpp"
+#include "hawkes_kernels.hpp"
+
+namespace hawkes {
+
+constexpr double kShiftMixed = 120.0;       // base-2 shift of the mixed pass's terms
+constexpr double kFloorMixed = -60.0;       // flag when lambda * 2^S < cmax * 2^-60
+constexpr double kFloorFp64 = -900.0;       // flag when lambda < cmax * 2^-900
+constexpr int kFixGrid = 256;
+constexpr int kTargetItems = 2048;
+constexpr int kNumStages = 12;
+
+struct Layout {
+  int64_t n = 0;
+  int d = 0, mixed = 0;
+  int nb = 0, n_pad = 0, L = 1, items = 0, nblk = 0;
+  size_t off_status, off_dconst, off_out8, off_items, off_band, off_rec, off_first, off_ps, off_prow, off_pcol,
+      off_sums, off_sigma, off_flags, off_list, off_logl, off_bpart, off_gfix, total;
+};
+
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+static int tiles_per_item(int64_t n) {
+  if (const char* e = std::getenv("HAWKES_TILES_PER_ITEM")) {
+    const int v = std::atoi(e);
+    if (v > 0) return v;
+  }
+  const int nb = (int)((n + kBandRows - 1) / kBandRows);
+  int64_t tiles = 0;
+  for (int b = 0; b < nb; ++b) tiles += (std::min<int64_t>(n, (int64_t)(b + 1) * kBandRows) + kTile - 1) / kTile;
+  return (int)std::max<int64_t>(1, (tiles + kTargetItems - 1) / kTargetItems);
+}
+
+static bool make_layout(int64_t n, int d, int prec, Layout& Lo) {
+  if (n < 2 || n > (int64_t(1) << 30) || d < 1 || d > kMaxD || (prec != HAWKES_FP64 && prec != HAWKES_MIXED))
+    return false;
+  Lo.n = n;
+  Lo.d = d;
+  Lo.mixed = prec == HAWKES_MIXED;
+  Lo.nb = (int)((n + kBandRows - 1) / kBandRows);
+  Lo.n_pad = Lo.nb * kBandRows;
+  Lo.L = tiles_per_item(n);
+  Lo.items = 0;
+  for (int b = 0; b < Lo.nb; ++b) {
+    const int64_t nt = (std::min<int64_t>(n, (int64_t)(b + 1) * kBandRows) + kTile - 1) / kTile;
+    Lo.items += (int)((nt + Lo.L - 1) / Lo.L);
+  }
+  Lo.nblk = (int)((n + 255) / 256);
+  const size_t real = Lo.mixed ? 4 : 8;
+  const int rw = Lo.mixed ? ((d + 2 + 3) / 4) * 4 : ((d + 2 + 1) / 2) * 2;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+  Lo.off_status = take(sizeof(int) * kStSlots);
+  Lo.off_dconst = take(sizeof(double) * 16);
+  Lo.off_out8 = take(sizeof(double) * 8);
+  Lo.off_items = take(sizeof(int2) * (size_t)Lo.items);
+  Lo.off_band = take(sizeof(int2) * (size_t)Lo.nb);
+  Lo.off_rec = take(real * rw * (size_t)Lo.n_pad);
+  Lo.off_first = take(sizeof(int) * (size_t)Lo.n_pad);
+  Lo.off_ps = take(real * (size_t)Lo.n_pad);
+  Lo.off_prow = take(sizeof(double) * (size_t)Lo.items * std::max(6, d) * kBandRows);
+  Lo.off_pcol = take(real * (size_t)Lo.nb * std::max(3, d) * Lo.n_pad);
+  Lo.off_sums = take(sizeof(double) * 6 * (size_t)n);
+  Lo.off_sigma = take(sizeof(double) * (size_t)n);
+  Lo.off_flags = take(sizeof(int) * (size_t)n);
+  Lo.off_list = take(sizeof(int) * (size_t)n);
+  Lo.off_logl = take(sizeof(double) * (size_t)n);
+  Lo.off_bpart = take(sizeof(double) * 8 * (size_t)Lo.nblk);
+  Lo.off_gfix = take(sizeof(double) * (size_t)d * n);
+  Lo.total = o;
+  return true;
+}
+
+static bool valid_params(const hawkes_params_t* p) {
+  const double v[6] = {p->mu, p->h, p->tau, p->theta, p->omega, p->xi};
+  for (double a : v)
+    if (!std::isfinite(a)) return false;
+  if (!(p->h > 0) || !(p->tau > 0) || !(p->omega > 0) || !(p->xi > 0)) return false;
+  if (p->mu < 0 || p->theta < 0 || (p->mu == 0 && p->theta == 0)) return false;
+  return true;
+}
+
+static KParams make_kparams(const Layout& Lo, const hawkes_params_t* p) {
+  KParams k;
+  std::memset(&k, 0, sizeof(k));
+  const int D = Lo.d;
+  const double two_pi = 6.283185307179586476925286766559;
+  const double log2e = 1.4426950408889634073599246810019;
+  k.n = (int)Lo.n;
+  k.n_pad = Lo.n_pad;
+  k.nb = Lo.nb;
+  k.L = Lo.L;
+  k.items = Lo.items;
+  k.d = D;
+  k.mu0 = p->mu;
+  k.tau_x = p->h;
+  k.tau_t = p->tau;
+  k.theta = p->theta;
+  k.omega = p->omega;
+  k.h = p->xi;
+  k.cbg_unit = std::pow(two_pi, -0.5 * (D + 1)) * std::pow(k.tau_x, -D) / k.tau_t;
+  k.cse_unit = k.omega * std::pow(two_pi, -0.5 * D) * std::pow(k.h, -D);
+  k.cbg = k.mu0 * k.cbg_unit;
+  k.cse = k.theta * k.cse_unit;
+  k.log_cbg = k.cbg > 0 ? std::log(k.cbg) : -INFINITY;
+  k.log_cse = k.cse > 0 ? std::log(k.cse) : -INFINITY;
+  k.cmax = std::max(k.cbg, k.cse);
+  k.alpha = 0.5 / (k.tau_x * k.tau_x);
+  k.beta = 0.5 / (k.tau_t * k.tau_t);
+  k.gamma = 0.5 / (k.h * k.h);
+  k.itx2 = 1.0 / (k.tau_x * k.tau_x);
+  k.ih2 = 1.0 / (k.h * k.h);
+  k.Ab = (float)(log2e * k.alpha);
+  k.Bt = (float)(log2e * k.beta);
+  k.Gs = (float)(log2e * k.gamma);
+  k.Ws = (float)(log2e * k.omega);
+  k.mixed = Lo.mixed;
+  k.S = Lo.mixed ? (float)kShiftMixed : 0.f;
+  k.sigma_main = Lo.mixed ? -kShiftMixed * std::log(2.0) : 0.0;
+  k.flag_floor = Lo.mixed ? kFloorMixed : kFloorFp64;
+  return k;
+}
+
+template <typename T>
+static T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// Optional per-stage timing (hawkes_grad_timed): events recorded before each
+// launch on the call's stream.
+struct StageTimer {
+  hipEvent_t ev[kNumStages + 1];
+  int used = 0;
+};
+static thread_local StageTimer* g_timer = nullptr;
+
+static inline void mark(hipStream_t s, int stage) {
+  if (g_timer) {
+    hipEventRecord(g_timer->ev[stage], s);
+    g_timer->used = stage + 1;
+  }
+}
+
+template <int D, bool MIX>
+static void launch_all(const Layout& Lo, const KParams& kp, const double* x, const double* t, void* ws,
+                       hipStream_t s, double* out8, double* grad_x) {
+  using Tr = Traits<D, MIX>;
+  using Rec = typename Tr::Rec;
+  using Real = typename Tr::Real;
+  using ColT = typename Tr::ColT;
+  int* status = at<int>(ws, Lo.off_status);
+  double* dconst = at<double>(ws, Lo.off_dconst);
+  int2* items = at<int2>(ws, Lo.off_items);
+  int2* band = at<int2>(ws, Lo.off_band);
+  Rec* rec = at<Rec>(ws, Lo.off_rec);
+  int* first = at<int>(ws, Lo.off_first);
+  Real* ps = at<Real>(ws, Lo.off_ps);
+  double* prow = at<double>(ws, Lo.off_prow);
+  ColT* pcol = at<ColT>(ws, Lo.off_pcol);
+  double* sums = at<double>(ws, Lo.off_sums);
+  double* sigma = at<double>(ws, Lo.off_sigma);
+  int* flags = at<int>(ws, Lo.off_flags);
+  int* list = at<int>(ws, Lo.off_list);
+  double* logl = at<double>(ws, Lo.off_logl);
+  double* bpart = at<double>(ws, Lo.off_bpart);
+  double* gfix = at<double>(ws, Lo.off_gfix);
+  const int n = (int)Lo.n;
+  const int g_ev = (n + 255) / 256;
+
+  mark(s, 0);
+  k_prep<D><<<1, 1024, 0, s>>>(x, t, n, Lo.nb, Lo.L, status, dconst, items, band);
+  mark(s, 1);
+  k_pack<D, MIX><<<Lo.n_pad / 256, 256, 0, s>>>(x, t, n, Lo.n_pad, status, dconst, rec, first, ps);
+  mark(s, 2);
+  if constexpr (MIX) k_pass1_mixed<D><<<Lo.items, kThreads, 0, s>>>(rec, first, items, status, prow, pcol, kp);
+  else k_pass1<D, MIX><<<Lo.items, kThreads, 0, s>>>(rec, first, items, status, prow, pcol, kp);
+  mark(s, 3);
+  k_reduce1<MIX, ColT><<<g_ev, 256, 0, s>>>(prow, pcol, band, status, sums, sigma, flags, kp);
+  mark(s, 4);
+  k_flaglist<<<1, 1024, 0, s>>>(flags, n, status, list);
+  mark(s, 5);
+  k_fix1<D><<<kFixGrid, 256, 0, s>>>(x, t, status, list, sums, sigma, kp);
+  mark(s, 6);
+  k_final1<D, MIX><<<Lo.nblk, 256, 0, s>>>(t, status, dconst, sums, sigma, flags, rec, ps, logl, bpart, kp);
+  mark(s, 7);
+  k_final2<<<1, 256, 0, s>>>(bpart, Lo.nblk, status, out8);
+  mark(s, 8);
+  if (grad_x) {
+    if constexpr (MIX) k_pass2_mixed<D><<<Lo.items, kThreads, 0, s>>>(rec, first, items, status, ps, prow, pcol, kp);
+    else k_pass2<D, MIX><<<Lo.items, kThreads, 0, s>>>(rec, first, items, status, ps, prow, pcol, kp);
+    mark(s, 9);
+    k_fix2b<D><<<g_ev, 256, 0, s>>>(x, t, status, list, logl, gfix, kp);
+    mark(s, 10);
+    k_fix2a<D><<<kFixGrid, 256, 0, s>>>(x, t, status, list, logl, gfix, kp);
+    mark(s, 11);
+    k_reduce2<D, ColT><<<g_ev, 256, 0, s>>>(prow, pcol, band, status, gfix, grad_x, kp);
+    mark(s, 12);
+  }
+}
+
+template <bool MIX>
+static void dispatch_d(int d, const Layout& Lo, const KParams& kp, const double* x, const double* t, void* ws,
+                       hipStream_t s, double* out8, double* grad_x) {
+  switch (d) {
+    case 1: launch_all<1, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
+    case 2: launch_all<2, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
+    case 3: launch_all<3, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
+    case 4: launch_all<4, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
+    case 5: launch_all<5, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
+    case 6: launch_all<6, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
+    case 7: launch_all<7, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
+    case 8: launch_all<8, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
+  }
+}
+
+// Host-side checks shared by every entry point.
+static int check_args(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec,
+                      void* ws, size_t ws_bytes, Layout& Lo) {
+  if (!x || !t || !p || !ws) return HAWKES_EINVAL;
+  if (!make_layout(n, d, prec, Lo)) return HAWKES_EINVAL;
+  if (ws_bytes < Lo.total) return HAWKES_EINVAL;
+  if (!valid_params(p)) return HAWKES_EPARAM;
+  return HAWKES_OK;
+}
+
+int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
+              size_t ws_bytes, void* stream, double* out8, double* grad_x) {
+  Layout Lo;
+  const int st = check_args(x, t, n, d, p, prec, ws, ws_bytes, Lo);
+  if (st != HAWKES_OK) return st;
+  if (!out8) return HAWKES_EINVAL;
+  const KParams kp = make_kparams(Lo, p);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  if (Lo.mixed) dispatch_d<true>(d, Lo, kp, x, t, ws, s, out8, grad_x);
+  else dispatch_d<false>(d, Lo, kp, x, t, ws, s, out8, grad_x);
+  return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+}
+
+static int run_sync(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
+                    size_t ws_bytes, void* stream, double* loglik, double* grad_x, double* grad_params) {
+  Layout Lo;
+  if (!ws || !make_layout(n, d, prec, Lo)) return HAWKES_EINVAL;
+  double* out8 = at<double>(ws, Lo.off_out8);
+  int st = run_async(x, t, n, d, p, prec, ws, ws_bytes, stream, out8, grad_x);
+  if (st != HAWKES_OK) return st;
+  double h[8];
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(h, out8, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return HAWKES_EDEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return HAWKES_EDEVICE;
+  st = (int)h[7];
+  if (st == HAWKES_EDATA) return st;
+  if (loglik) *loglik = h[0];
+  if (grad_params)
+    for (int k = 0; k < 6; ++k) grad_params[k] = h[1 + k];
+  return st;
+}
+
+}  // namespace hawkes
+
+extern "C" {
+
+size_t hawkes_workspace_bytes(int64_t n, int d, int prec) {
+  hawkes::Layout Lo;
+  return hawkes::make_layout(n, d, prec, Lo) ? Lo.total : 0;
+}
+
+int hawkes_loglik(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
+                  size_t ws_bytes, void* stream, double* loglik) {
+  if (!loglik) return HAWKES_EINVAL;
+  return hawkes::run_sync(x, t, n, d, p, prec, ws, ws_bytes, stream, loglik, nullptr, nullptr);
+}
+
+int hawkes_grad(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
+                size_t ws_bytes, void* stream, double* loglik, double* grad_x, double* grad_params) {
+  if (!grad_x) return HAWKES_EINVAL;
+  return hawkes::run_sync(x, t, n, d, p, prec, ws, ws_bytes, stream, loglik, grad_x, grad_params);
+}
+
+int hawkes_grad_async(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec,
+                      void* ws, size_t ws_bytes, void* stream, double* out8, double* grad_x) {
+  return hawkes::run_async(x, t, n, d, p, prec, ws, ws_bytes, stream, out8, grad_x);
+}
+
+const char* hawkes_strerror(int status) {
+  switch (status) {
+    case HAWKES_OK: return "ok";
+    case HAWKES_EINVAL: return "invalid argument (n < 2, d outside [1,8], null pointer or workspace too small)";
+    case HAWKES_EPARAM: return "parameter non-finite or outside its domain";
+    case HAWKES_EDATA: return "data invalid (times unsorted, negative or non-finite; locations non-finite)";
+    case HAWKES_EZERORATE: return "some event has zero rate: log-likelihood is -inf";
+    case HAWKES_ENOMEM: return "request footprint exceeds the memory budget";
+    case HAWKES_EDEVICE: return "HIP runtime error";
+    case HAWKES_ESTATE: return "unknown ticket or dataset, or server shutting down";
+    case HAWKES_ETIMEOUT: return "wait timed out";
+    case HAWKES_EPENDING: return "request pending";
+    default: return "unknown status";
+  }
+}
+
+const char* hawkes_version(void) { return "0.1.0"; }
+
+int hawkes_grad_timed(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec,
+                      void* ws, size_t ws_bytes, void* stream, double* loglik, double* grad_x, double* grad_params,
+                      float* stage_ms) {
+  if (!stage_ms) return HAWKES_EINVAL;
+  hawkes::StageTimer tm;
+  for (int k = 0; k <= hawkes::kNumStages; ++k)
+    if (hipEventCreate(&tm.ev[k]) != hipSuccess) return HAWKES_EDEVICE;
+  hawkes::g_timer = &tm;
+  const int st = hawkes::run_sync(x, t, n, d, p, prec, ws, ws_bytes, stream, loglik, grad_x, grad_params);
+  hawkes::g_timer = nullptr;
+  for (int k = 0; k < hawkes::kNumStages; ++k) stage_ms[k] = 0.f;
+  if (st == HAWKES_OK || st == HAWKES_EZERORATE) {
+    hipEventSynchronize(tm.ev[tm.used - 1]);
+    for (int k = 0; k + 1 < tm.used; ++k) hipEventElapsedTime(&stage_ms[k], tm.ev[k], tm.ev[k + 1]);
+  }
+  for (int k = 0; k <= hawkes::kNumStages; ++k) hipEventDestroy(tm.ev[k]);
+  return st;
+}
+
+}  // extern "C"

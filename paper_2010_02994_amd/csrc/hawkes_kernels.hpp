@@ -1,0 +1,1107 @@
+// gfx950 kernels of the Hawkes log-likelihood + gradient hot path.
+//
+// Notation (Sec. 2.1 of arXiv 2010.02994): for the ordered pair (i, j) with
+// j earlier in time, r2 = |x_i - x_j|^2 and dt = t_i - t_j >= 0.
+//   background term (symmetric)   e_bg = exp(-r2/(2 tau_x^2) - dt^2/(2 tau_t^2)),  dt != 0
+//   excitation term (j -> i)      e_se = exp(-omega dt - r2/(2 h^2)),              dt > 0
+// The weighted pair terms are mu_ij = c_bg e_bg and xi_ij = c_se e_se.
+//
+// Pass 1 accumulates, per event, the six unweighted sums
+//   K = sum e_bg, R = sum e_bg r2, U = sum e_bg dt^2, J = sum e_se, V = sum e_se r2, W = sum e_se dt
+// (K, R, U receive the pair from both endpoints; J, V, W only at the later one).
+// Pass 2 accumulates the location gradient of App. A, scattering each
+// unordered pair's coefficient into both endpoints.
+//
+// Mixed precision: coordinates are float32 offsets from the data center, the
+// exponent is formed in base 2 with a constant shift S (terms carry a factor
+// 2^S), exp is v_exp_f32, and per-tile float32 partials fold into float64.
+// Rows whose rate sits below the shifted window are recomputed in float64 by
+// the fix-up kernels (k_fix1, k_fix2a/b), so no event loses range.
+#pragma once
+#include "hawkes_common.hpp"
+
+namespace hawkes {
+
+template <int D, bool MIX> struct Traits;
+template <int D> struct Traits<D, true> {
+  using Real = float;
+  using ColT = float;
+  static constexpr int RW = ((D + 2 + 3) / 4) * 4;  // record words: coords, t, aux, pad
+  struct alignas(16) Rec { float v[RW]; };
+};
+template <int D> struct Traits<D, false> {
+  using Real = double;
+  using ColT = double;
+  static constexpr int RW = ((D + 2 + 1) / 2) * 2;
+  struct alignas(16) Rec { double v[RW]; };
+};
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ float exp_pair(float z) { return __builtin_amdgcn_exp2f(z); }
+__device__ __forceinline__ double exp_pair(double z) { return exp(z); }
+
+template <typename T>
+__device__ __forceinline__ T block_sum_256(T v, T* sh) {
+  // fixed-shape tree over 256 threads (deterministic)
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  T r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double block_max_256(double v, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] = fmax(sh[tid], sh[tid + s]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------ prepare / pack
+
+// One workgroup of 1024 threads: validates the data, finds the data center
+// (mixed path), t_N, and writes the work-item table of the pair passes.
+// Items run band-major from the last (longest) band to the first.
+template <int D>
+__global__ void __launch_bounds__(1024) k_prep(const double* __restrict__ x, const double* __restrict__ t, int n,
+                                                int nb, int L, int* __restrict__ status,
+                                                double* __restrict__ dconst, int2* __restrict__ items,
+                                                int2* __restrict__ band_info) {
+  __shared__ double s_min[kMaxD + 1][32], s_max[kMaxD + 1][32];
+  __shared__ int s_bad[32];
+  __shared__ int s_scan[1024];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double mn[kMaxD + 1], mx[kMaxD + 1];
+#pragma unroll
+  for (int k = 0; k <= kMaxD; ++k) { mn[k] = INFINITY; mx[k] = -INFINITY; }
+  int bad = 0;
+  for (int i = tid; i < n; i += 1024) {
+    const double ti = t[i];
+    if (!isfinite(ti) || ti < 0.0) bad = 1;
+    if (i > 0 && !(ti >= t[i - 1])) bad = 1;
+    mn[kMaxD] = fmin(mn[kMaxD], ti);
+    mx[kMaxD] = fmax(mx[kMaxD], ti);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double v = x[(int64_t)i * D + k];
+      if (!isfinite(v)) bad = 1;
+      mn[k] = fmin(mn[k], v);
+      mx[k] = fmax(mx[k], v);
+    }
+  }
+  // wave reductions, then across the 16 waves in fixed order
+#pragma unroll
+  for (int k = 0; k <= kMaxD; ++k) {
+    for (int off = 32; off > 0; off >>= 1) {
+      mn[k] = fmin(mn[k], __shfl_xor(mn[k], off));
+      mx[k] = fmax(mx[k], __shfl_xor(mx[k], off));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) bad |= __shfl_xor(bad, off);
+  if (lane == 0) {
+    for (int k = 0; k <= kMaxD; ++k) { s_min[k][w] = mn[k]; s_max[k][w] = mx[k]; }
+    s_bad[w] = bad;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int b = 0;
+    double a[kMaxD + 1], z[kMaxD + 1];
+    for (int k = 0; k <= kMaxD; ++k) { a[k] = INFINITY; z[k] = -INFINITY; }
+    for (int ww = 0; ww < 16; ++ww) {
+      b |= s_bad[ww];
+      for (int k = 0; k <= kMaxD; ++k) { a[k] = fmin(a[k], s_min[k][ww]); z[k] = fmax(z[k], s_max[k][ww]); }
+    }
+    status[kStData] = b ? -3 : 0;
+    status[kStZero] = 0;
+    status[kStFlagCount] = 0;
+    dconst[0] = t[n - 1];                       // t_N (largest time for sorted input)
+    for (int k = 0; k < D; ++k) dconst[1 + k] = 0.5 * (a[k] + z[k]);
+    dconst[1 + kMaxD] = 0.5 * (a[kMaxD] + z[kMaxD]);
+  }
+  // work items: chunks of band b = ceil(ntiles_b / L), bands in descending order
+  const int per = (nb + 1023) / 1024;
+  int local = 0;
+  for (int q = 0; q < per; ++q) {
+    const int pos = tid * per + q;      // position in descending band order
+    if (pos < nb) {
+      const int b = nb - 1 - pos;
+      const int row_end = min(n, (b + 1) * kBandRows);
+      const int nt = (row_end + kTile - 1) / kTile;
+      local += (nt + L - 1) / L;
+    }
+  }
+  s_scan[tid] = local;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = tid >= off ? s_scan[tid - off] : 0;
+    __syncthreads();
+    s_scan[tid] += v;
+    __syncthreads();
+  }
+  int base = s_scan[tid] - local;
+  for (int q = 0; q < per; ++q) {
+    const int pos = tid * per + q;
+    if (pos < nb) {
+      const int b = nb - 1 - pos;
+      const int row_end = min(n, (b + 1) * kBandRows);
+      const int nt = (row_end + kTile - 1) / kTile;
+      const int ch = (nt + L - 1) / L;
+      band_info[b] = make_int2(base, ch);
+      for (int c = 0; c < ch; ++c) items[base + c] = make_int2(b, c);
+      base += ch;
+    }
+  }
+}
+
+// Packed records and tie groups.  first[i] is the first index with t == t[i]
+// (sorted input), so for j < i: t_j < t_i  <=>  j < first[i].  Padded rows get
+// first = 0, which makes every pair with them inactive.
+template <int D, bool MIX>
+__global__ void __launch_bounds__(256) k_pack(const double* __restrict__ x, const double* __restrict__ t, int n,
+                                               int n_pad, const int* __restrict__ status,
+                                               const double* __restrict__ dconst,
+                                               typename Traits<D, MIX>::Rec* __restrict__ rec, int* __restrict__ first,
+                                               typename Traits<D, MIX>::Real* __restrict__ psrow) {
+  using Tr = Traits<D, MIX>;
+  using Real = typename Tr::Real;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad || status[kStData] != 0) return;
+  typename Tr::Rec r;
+#pragma unroll
+  for (int k = 0; k < Tr::RW; ++k) r.v[k] = Real(0);
+  int f = 0;
+  if (i < n) {
+    const double ti = t[i];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double v = x[(int64_t)i * D + k];
+      r.v[k] = MIX ? Real(v - dconst[1 + k]) : Real(v);
+    }
+    r.v[D] = MIX ? Real(ti - dconst[1 + kMaxD]) : Real(ti);
+    int lo = 0, hi = i;   // lower_bound of ti in t[0..i]
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (t[mid] < ti) lo = mid + 1; else hi = mid;
+    }
+    f = lo;
+  }
+  rec[i] = r;
+  first[i] = f;
+  psrow[i] = Real(0);
+}
+
+// ------------------------------------------------------------ pair passes
+
+// Stage one tile of 64 records into LDS (16-byte chunks).
+template <typename Rec>
+struct TileStage {
+  static constexpr int kChunks = 64 * (int)sizeof(Rec) / 16;
+  static constexpr int kPer = (kChunks + kThreads - 1) / kThreads;
+  uint4 r[kPer];
+  __device__ __forceinline__ void load(const Rec* __restrict__ src, int tile) {
+    const uint4* s = reinterpret_cast<const uint4*>(src + (int64_t)tile * kTile);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int c = threadIdx.x + k * kThreads;
+      if (c < kChunks) r[k] = s[c];
+    }
+  }
+  __device__ __forceinline__ void store(Rec* dst) {
+    uint4* s = reinterpret_cast<uint4*>(dst);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int c = threadIdx.x + k * kThreads;
+      if (c < kChunks) s[c] = r[k];
+    }
+  }
+};
+
+// Pass 1: rates and the moments the parameter gradient needs.
+template <int D, bool MIX>
+struct Pass1Rows {
+  using Real = typename Traits<D, MIX>::Real;
+  static constexpr int R = kRowsPerLane;
+  Real x[R][D], t[R];
+  int first[R];
+  Real a[R][6];        // per-tile partials (float32 in mixed, the running sums in float64)
+  double acc[R][6];    // float64 running sums (mixed path only)
+};
+
+template <int D, bool MIX, bool MASK>
+__device__ __forceinline__ void pass1_tile(Pass1Rows<D, MIX>& S, const typename Traits<D, MIX>::Rec* __restrict__ cols,
+                                           typename Traits<D, MIX>::ColT* __restrict__ acc_w, int tile_base,
+                                           const KParams& kp) {
+  using Real = typename Traits<D, MIX>::Real;
+  constexpr int R = kRowsPerLane;
+  const int lane = threadIdx.x & 63;
+  // base-2 (mixed) or natural (float64) exponent scales
+  const Real cb = MIX ? Real(kp.Ab) : Real(kp.alpha);
+  const Real ct = MIX ? Real(kp.Bt) : Real(kp.beta);
+  const Real cg = MIX ? Real(kp.Gs) : Real(kp.gamma);
+  const Real cw = MIX ? Real(kp.Ws) : Real(kp.omega);
+  const Real sh = MIX ? Real(kp.S) : Real(0);
+#pragma unroll 4
+  for (int k = 0; k < 64; ++k) {
+    const int c = lane ^ k;
+    const auto col = cols[c];
+    Real cK = 0, cR = 0, cU = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      Real r2 = 0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const Real dx = S.x[r][q] - col.v[q];
+        r2 = dx * dx + r2;
+      }
+      const Real dt = S.t[r] - col.v[D];
+      const Real u = cb * r2;
+      const Real v = ct * (dt * dt);
+      const Real ys = cg * r2;
+      const Real ws = cw * dt;
+      Real eb = exp_pair((sh - u) - v);
+      Real es = exp_pair((sh - ys) - ws);
+      if (MASK) {
+        const bool act = (tile_base + c) < S.first[r];
+        eb = act ? eb : Real(0);
+        es = act ? es : Real(0);
+      }
+      // the float64 path accumulates raw r2, dt^2, dt; the mixed path the
+      // dimensionless exponent parts (rescaled when the sums are reduced)
+      const Real mu_ = MIX ? u : r2;
+      const Real mv_ = MIX ? v : dt * dt;
+      const Real my_ = MIX ? ys : r2;
+      const Real mw_ = MIX ? ws : dt;
+      S.a[r][0] += eb;
+      S.a[r][1] = eb * mu_ + S.a[r][1];
+      S.a[r][2] = eb * mv_ + S.a[r][2];
+      S.a[r][3] += es;
+      S.a[r][4] = es * my_ + S.a[r][4];
+      S.a[r][5] = es * mw_ + S.a[r][5];
+      cK += eb;
+      cR = eb * mu_ + cR;
+      cU = eb * mv_ + cU;
+    }
+    atomicAdd(&acc_w[0 * 64 + c], cK);
+    atomicAdd(&acc_w[1 * 64 + c], cR);
+    atomicAdd(&acc_w[2 * 64 + c], cU);
+  }
+}
+
+template <int D, bool MIX>
+__global__ void __launch_bounds__(kThreads) k_pass1(const typename Traits<D, MIX>::Rec* __restrict__ rec,
+                                                     const int* __restrict__ first, const int2* __restrict__ items,
+                                                     const int* __restrict__ status, double* __restrict__ prow,
+                                                     typename Traits<D, MIX>::ColT* __restrict__ pcol, KParams kp) {
+  using Tr = Traits<D, MIX>;
+  using Real = typename Tr::Real;
+  using ColT = typename Tr::ColT;
+  using Rec = typename Tr::Rec;
+  constexpr int R = kRowsPerLane;
+  constexpr int NQ = 3;
+  __shared__ Rec s_rec[2][kTile];
+  __shared__ ColT s_acc[2][kWaves][NQ][kTile];
+  if (status[kStData] != 0) return;
+  const int2 it = items[blockIdx.x];
+  const int band = it.x, chunk = it.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row_base = band * kBandRows;
+  const int row_end = min(kp.n, row_base + kBandRows);
+  const int nt_band = (row_end + kTile - 1) / kTile;
+  const int tile0 = chunk * kp.L;
+  const int tile1 = min(tile0 + kp.L, nt_band);
+  const bool partial_band = row_base + kBandRows > kp.n;
+  const int first_min = first[row_base];
+
+  Pass1Rows<D, MIX> S;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int gi = row_base + wave * 64 * R + r * 64 + lane;
+    const Rec rr = rec[gi];
+#pragma unroll
+    for (int q = 0; q < D; ++q) S.x[r][q] = rr.v[q];
+    S.t[r] = rr.v[D];
+    S.first[r] = first[gi];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) { S.a[r][q] = 0; S.acc[r][q] = 0.0; }
+  }
+  {
+    ColT* z = &s_acc[0][0][0][0];
+    for (int i = threadIdx.x; i < 2 * kWaves * NQ * kTile; i += kThreads) z[i] = ColT(0);
+  }
+  TileStage<Rec> stage;
+  stage.load(rec, tile0);
+  for (int tile = tile0; tile < tile1; ++tile) {
+    const int buf = (tile - tile0) & 1;
+    stage.store(s_rec[buf]);
+    __syncthreads();
+    if (tile + 1 < tile1) stage.load(rec, tile + 1);
+    if (tile > tile0 && threadIdx.x < NQ * kTile) {
+      // column sums of the previous tile: fixed-order sum over the waves
+      const int q = threadIdx.x >> 6, c = threadIdx.x & 63;
+      ColT s = ColT(0);
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) { s += s_acc[buf ^ 1][w][q][c]; s_acc[buf ^ 1][w][q][c] = ColT(0); }
+      pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
+    }
+    const bool full = !partial_band && (tile + 1) * kTile <= first_min;
+    if (full) pass1_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    else pass1_tile<D, MIX, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    if (MIX) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) { S.acc[r][q] += (double)S.a[r][q]; S.a[r][q] = 0; }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ * kTile) {
+    const int buf = (tile1 - 1 - tile0) & 1;
+    const int q = threadIdx.x >> 6, c = threadIdx.x & 63;
+    ColT s = ColT(0);
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += s_acc[buf][w][q][c];
+    pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile1 - 1) * kTile + c] = s;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int lr = wave * 64 * R + r * 64 + lane;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      prow[((int64_t)blockIdx.x * 6 + q) * kBandRows + lr] = MIX ? S.acc[r][q] : (double)S.a[r][q];
+  }
+}
+
+// Pass 2: location gradient.  For the pair (i later, j earlier)
+//   c_ij = mu_ij (1/lambda_i + 1/lambda_j)/tau_x^2 + xi_ij/(lambda_i h^2)
+// and d ell/d x_i += c_ij (x_j - x_i), d ell/d x_j += c_ij (x_i - x_j)   (App. A).
+// Per event: pb = c_bg 2^-S/(lambda~ tau_x^2) in the record's aux slot (the
+// column side), ps = c_se 2^-S/(lambda~ h^2) for the row side; both are 0 for
+// rows the fix-up kernels handle.
+template <int D, bool MIX>
+struct Pass2Rows {
+  using Real = typename Traits<D, MIX>::Real;
+  static constexpr int R = kRowsPerLane;
+  Real x[R][D], t[R], pb[R], ps[R];
+  int first[R];
+  Real g[R][D];
+  double acc[R][D];
+};
+
+template <int D, bool MIX, bool MASK>
+__device__ __forceinline__ void pass2_tile(Pass2Rows<D, MIX>& S, const typename Traits<D, MIX>::Rec* __restrict__ cols,
+                                           typename Traits<D, MIX>::ColT* __restrict__ acc_w, int tile_base,
+                                           const KParams& kp) {
+  using Real = typename Traits<D, MIX>::Real;
+  constexpr int R = kRowsPerLane;
+  const int lane = threadIdx.x & 63;
+  const Real cb = MIX ? Real(kp.Ab) : Real(kp.alpha);
+  const Real ct = MIX ? Real(kp.Bt) : Real(kp.beta);
+  const Real cg = MIX ? Real(kp.Gs) : Real(kp.gamma);
+  const Real cw = MIX ? Real(kp.Ws) : Real(kp.omega);
+  const Real sh = MIX ? Real(kp.S) : Real(0);
+#pragma unroll 4
+  for (int k = 0; k < 64; ++k) {
+    const int c = lane ^ k;
+    const auto col = cols[c];
+    Real cgr[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) cgr[q] = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      Real dx[D];
+      Real r2 = 0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        dx[q] = S.x[r][q] - col.v[q];
+        r2 = dx[q] * dx[q] + r2;
+      }
+      const Real dt = S.t[r] - col.v[D];
+      const Real zb = (sh - cb * r2) - ct * (dt * dt);
+      const Real zs = (sh - cg * r2) - cw * dt;
+      Real eb = exp_pair(zb);
+      Real es = exp_pair(zs);
+      if (MASK) {
+        const bool act = (tile_base + c) < S.first[r];
+        eb = act ? eb : Real(0);
+        es = act ? es : Real(0);
+      }
+      const Real coef = eb * (S.pb[r] + col.v[D + 1]) + es * S.ps[r];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        S.g[r][q] = -coef * dx[q] + S.g[r][q];
+        cgr[q] = coef * dx[q] + cgr[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) atomicAdd(&acc_w[q * 64 + c], cgr[q]);
+  }
+}
+
+template <int D, bool MIX>
+__global__ void __launch_bounds__(kThreads) k_pass2(const typename Traits<D, MIX>::Rec* __restrict__ rec,
+                                                     const int* __restrict__ first, const int2* __restrict__ items,
+                                                     const int* __restrict__ status,
+                                                     const typename Traits<D, MIX>::Real* __restrict__ psrow,
+                                                     double* __restrict__ prow,
+                                                     typename Traits<D, MIX>::ColT* __restrict__ pcol, KParams kp) {
+  using Tr = Traits<D, MIX>;
+  using Real = typename Tr::Real;
+  using ColT = typename Tr::ColT;
+  using Rec = typename Tr::Rec;
+  constexpr int R = kRowsPerLane;
+  constexpr int NQ = D;
+  __shared__ Rec s_rec[2][kTile];
+  __shared__ ColT s_acc[2][kWaves][NQ][kTile];
+  if (status[kStData] != 0 || status[kStZero] != 0) return;
+  const int2 it = items[blockIdx.x];
+  const int band = it.x, chunk = it.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row_base = band * kBandRows;
+  const int row_end = min(kp.n, row_base + kBandRows);
+  const int nt_band = (row_end + kTile - 1) / kTile;
+  const int tile0 = chunk * kp.L;
+  const int tile1 = min(tile0 + kp.L, nt_band);
+  const bool partial_band = row_base + kBandRows > kp.n;
+  const int first_min = first[row_base];
+
+  Pass2Rows<D, MIX> S;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int gi = row_base + wave * 64 * R + r * 64 + lane;
+    const Rec rr = rec[gi];
+#pragma unroll
+    for (int q = 0; q < D; ++q) { S.x[r][q] = rr.v[q]; S.g[r][q] = 0; S.acc[r][q] = 0.0; }
+    S.t[r] = rr.v[D];
+    S.pb[r] = rr.v[D + 1];
+    S.ps[r] = psrow[gi];
+    S.first[r] = first[gi];
+  }
+  {
+    ColT* z = &s_acc[0][0][0][0];
+    for (int i = threadIdx.x; i < 2 * kWaves * NQ * kTile; i += kThreads) z[i] = ColT(0);
+  }
+  TileStage<Rec> stage;
+  stage.load(rec, tile0);
+  for (int tile = tile0; tile < tile1; ++tile) {
+    const int buf = (tile - tile0) & 1;
+    stage.store(s_rec[buf]);
+    __syncthreads();
+    if (tile + 1 < tile1) stage.load(rec, tile + 1);
+    for (int e = threadIdx.x; tile > tile0 && e < NQ * kTile; e += kThreads) {
+      const int q = e >> 6, c = e & 63;
+      ColT s = ColT(0);
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) { s += s_acc[buf ^ 1][w][q][c]; s_acc[buf ^ 1][w][q][c] = ColT(0); }
+      pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
+    }
+    const bool full = !partial_band && (tile + 1) * kTile <= first_min;
+    if (full) pass2_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    else pass2_tile<D, MIX, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    if (MIX) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int q = 0; q < D; ++q) { S.acc[r][q] += (double)S.g[r][q]; S.g[r][q] = 0; }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NQ * kTile; e += kThreads) {
+    const int buf = (tile1 - 1 - tile0) & 1;
+    const int q = e >> 6, c = e & 63;
+    ColT s = ColT(0);
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += s_acc[buf][w][q][c];
+    pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile1 - 1) * kTile + c] = s;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int lr = wave * 64 * R + r * 64 + lane;
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      prow[((int64_t)blockIdx.x * D + q) * kBandRows + lr] = MIX ? S.acc[r][q] : (double)S.g[r][q];
+  }
+}
+
+// ------------------------------------------------ mixed-precision pair passes
+//
+// The float32 passes keep the symmetric (column) sums out of LDS atomics:
+// at step k of a 64-column tile, lane l pairs its rows with column (l + k) mod 64,
+// and the column accumulators rotate one lane per step with a DPP wave_rol:1
+// fused into the add (acc <- acc[lane + 1] + contribution).  After 64 steps
+// lane l holds the sums of column (l + 63) mod 64.  The tile's records sit in
+// LDS twice in a row, so the column read is lds[lane + k] with a constant offset.
+
+__device__ __forceinline__ float rol1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xf, 0xf, false));
+}
+
+template <int D, bool MASK>
+__device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const typename Traits<D, true>::Rec* __restrict__ cols,
+                                                 float* __restrict__ acc_w, int tile_base, const KParams& kp) {
+  constexpr int R = kRowsPerLane;
+  const int lane = threadIdx.x & 63;
+  const float cb = kp.Ab, ct = kp.Bt, cg = kp.Gs, cw = kp.Ws, sh = kp.S;
+  const typename Traits<D, true>::Rec* __restrict__ my = cols + lane;
+  float aK = 0.f, aR = 0.f, aU = 0.f;
+#pragma unroll 8
+  for (int k = 0; k < 64; ++k) {
+    const auto col = my[k];
+    float cK = 0.f, cR = 0.f, cU = 0.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      float r2 = 0.f;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const float dx = S.x[r][q] - col.v[q];
+        r2 = dx * dx + r2;
+      }
+      const float dt = S.t[r] - col.v[D];
+      const float u = cb * r2;
+      const float v = ct * (dt * dt);
+      const float ys = cg * r2;
+      const float ws = cw * dt;
+      float eb = __builtin_amdgcn_exp2f((sh - u) - v);
+      float es = __builtin_amdgcn_exp2f((sh - ys) - ws);
+      if (MASK) {
+        const bool act = (tile_base + ((lane + k) & 63)) < S.first[r];
+        eb = act ? eb : 0.f;
+        es = act ? es : 0.f;
+      }
+      S.a[r][0] += eb;
+      S.a[r][1] = eb * u + S.a[r][1];
+      S.a[r][2] = eb * v + S.a[r][2];
+      S.a[r][3] += es;
+      S.a[r][4] = es * ys + S.a[r][4];
+      S.a[r][5] = es * ws + S.a[r][5];
+      cK += eb;
+      cR = eb * u + cR;
+      cU = eb * v + cU;
+    }
+    aK = rol1(aK) + cK;
+    aR = rol1(aR) + cR;
+    aU = rol1(aU) + cU;
+  }
+  const int c = (lane + 63) & 63;
+  acc_w[0 * 64 + c] = aK;
+  acc_w[1 * 64 + c] = aR;
+  acc_w[2 * 64 + c] = aU;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kThreads) k_pass1_mixed(const typename Traits<D, true>::Rec* __restrict__ rec,
+                                                           const int* __restrict__ first, const int2* __restrict__ items,
+                                                           const int* __restrict__ status, double* __restrict__ prow,
+                                                           float* __restrict__ pcol, KParams kp) {
+  using Rec = typename Traits<D, true>::Rec;
+  constexpr int R = kRowsPerLane;
+  constexpr int NQ = 3;
+  __shared__ Rec s_rec[2][2 * kTile];
+  __shared__ float s_acc[2][kWaves][NQ][kTile];
+  if (status[kStData] != 0) return;
+  const int2 it = items[blockIdx.x];
+  const int band = it.x, chunk = it.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row_base = band * kBandRows;
+  const int row_end = min(kp.n, row_base + kBandRows);
+  const int nt_band = (row_end + kTile - 1) / kTile;
+  const int tile0 = chunk * kp.L;
+  const int tile1 = min(tile0 + kp.L, nt_band);
+  const bool partial_band = row_base + kBandRows > kp.n;
+  const int first_min = first[row_base];
+
+  Pass1Rows<D, true> S;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int gi = row_base + wave * 64 * R + r * 64 + lane;
+    const Rec rr = rec[gi];
+#pragma unroll
+    for (int q = 0; q < D; ++q) S.x[r][q] = rr.v[q];
+    S.t[r] = rr.v[D];
+    S.first[r] = first[gi];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) { S.a[r][q] = 0.f; S.acc[r][q] = 0.0; }
+  }
+  TileStage<Rec> stage;
+  stage.load(rec, tile0);
+  for (int tile = tile0; tile < tile1; ++tile) {
+    const int buf = (tile - tile0) & 1;
+    stage.store(&s_rec[buf][0]);
+    stage.store(&s_rec[buf][kTile]);
+    __syncthreads();
+    if (tile + 1 < tile1) stage.load(rec, tile + 1);
+    if (tile > tile0 && threadIdx.x < NQ * kTile) {
+      const int q = threadIdx.x >> 6, c = threadIdx.x & 63;
+      float s = 0.f;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) s += s_acc[buf ^ 1][w][q][c];
+      pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
+    }
+    const bool full = !partial_band && (tile + 1) * kTile <= first_min;
+    if (full) pass1_tile_mixed<D, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    else pass1_tile_mixed<D, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) { S.acc[r][q] += (double)S.a[r][q]; S.a[r][q] = 0.f; }
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ * kTile) {
+    const int buf = (tile1 - 1 - tile0) & 1;
+    const int q = threadIdx.x >> 6, c = threadIdx.x & 63;
+    float s = 0.f;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += s_acc[buf][w][q][c];
+    pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile1 - 1) * kTile + c] = s;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int lr = wave * 64 * R + r * 64 + lane;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) prow[((int64_t)blockIdx.x * 6 + q) * kBandRows + lr] = S.acc[r][q];
+  }
+}
+
+template <int D, bool MASK>
+__device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const typename Traits<D, true>::Rec* __restrict__ cols,
+                                                 float* __restrict__ acc_w, int tile_base, const KParams& kp) {
+  constexpr int R = kRowsPerLane;
+  const int lane = threadIdx.x & 63;
+  const float cb = kp.Ab, ct = kp.Bt, cg = kp.Gs, cw = kp.Ws, sh = kp.S;
+  const typename Traits<D, true>::Rec* __restrict__ my = cols + lane;
+  float ag[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) ag[q] = 0.f;
+#pragma unroll 8
+  for (int k = 0; k < 64; ++k) {
+    const auto col = my[k];
+    float cgr[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) cgr[q] = 0.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      float dx[D];
+      float r2 = 0.f;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        dx[q] = S.x[r][q] - col.v[q];
+        r2 = dx[q] * dx[q] + r2;
+      }
+      const float dt = S.t[r] - col.v[D];
+      const float zb = (sh - cb * r2) - ct * (dt * dt);
+      const float zs = (sh - cg * r2) - cw * dt;
+      float eb = __builtin_amdgcn_exp2f(zb);
+      float es = __builtin_amdgcn_exp2f(zs);
+      if (MASK) {
+        const bool act = (tile_base + ((lane + k) & 63)) < S.first[r];
+        eb = act ? eb : 0.f;
+        es = act ? es : 0.f;
+      }
+      const float coef = eb * (S.pb[r] + col.v[D + 1]) + es * S.ps[r];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        S.g[r][q] = -coef * dx[q] + S.g[r][q];
+        cgr[q] = coef * dx[q] + cgr[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) ag[q] = rol1(ag[q]) + cgr[q];
+  }
+  const int c = (lane + 63) & 63;
+#pragma unroll
+  for (int q = 0; q < D; ++q) acc_w[q * 64 + c] = ag[q];
+}
+
+template <int D>
+__global__ void __launch_bounds__(kThreads) k_pass2_mixed(const typename Traits<D, true>::Rec* __restrict__ rec,
+                                                           const int* __restrict__ first, const int2* __restrict__ items,
+                                                           const int* __restrict__ status, const float* __restrict__ psrow,
+                                                           double* __restrict__ prow, float* __restrict__ pcol,
+                                                           KParams kp) {
+  using Rec = typename Traits<D, true>::Rec;
+  constexpr int R = kRowsPerLane;
+  constexpr int NQ = D;
+  __shared__ Rec s_rec[2][2 * kTile];
+  __shared__ float s_acc[2][kWaves][NQ][kTile];
+  if (status[kStData] != 0 || status[kStZero] != 0) return;
+  const int2 it = items[blockIdx.x];
+  const int band = it.x, chunk = it.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row_base = band * kBandRows;
+  const int row_end = min(kp.n, row_base + kBandRows);
+  const int nt_band = (row_end + kTile - 1) / kTile;
+  const int tile0 = chunk * kp.L;
+  const int tile1 = min(tile0 + kp.L, nt_band);
+  const bool partial_band = row_base + kBandRows > kp.n;
+  const int first_min = first[row_base];
+
+  Pass2Rows<D, true> S;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int gi = row_base + wave * 64 * R + r * 64 + lane;
+    const Rec rr = rec[gi];
+#pragma unroll
+    for (int q = 0; q < D; ++q) { S.x[r][q] = rr.v[q]; S.g[r][q] = 0.f; S.acc[r][q] = 0.0; }
+    S.t[r] = rr.v[D];
+    S.pb[r] = rr.v[D + 1];
+    S.ps[r] = psrow[gi];
+    S.first[r] = first[gi];
+  }
+  TileStage<Rec> stage;
+  stage.load(rec, tile0);
+  for (int tile = tile0; tile < tile1; ++tile) {
+    const int buf = (tile - tile0) & 1;
+    stage.store(&s_rec[buf][0]);
+    stage.store(&s_rec[buf][kTile]);
+    __syncthreads();
+    if (tile + 1 < tile1) stage.load(rec, tile + 1);
+    for (int e = threadIdx.x; tile > tile0 && e < NQ * kTile; e += kThreads) {
+      const int q = e >> 6, c = e & 63;
+      float s = 0.f;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) s += s_acc[buf ^ 1][w][q][c];
+      pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
+    }
+    const bool full = !partial_band && (tile + 1) * kTile <= first_min;
+    if (full) pass2_tile_mixed<D, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    else pass2_tile_mixed<D, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int q = 0; q < D; ++q) { S.acc[r][q] += (double)S.g[r][q]; S.g[r][q] = 0.f; }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < NQ * kTile; e += kThreads) {
+    const int buf = (tile1 - 1 - tile0) & 1;
+    const int q = e >> 6, c = e & 63;
+    float s = 0.f;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += s_acc[buf][w][q][c];
+    pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile1 - 1) * kTile + c] = s;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int lr = wave * 64 * R + r * 64 + lane;
+#pragma unroll
+    for (int q = 0; q < D; ++q) prow[((int64_t)blockIdx.x * D + q) * kBandRows + lr] = S.acc[r][q];
+  }
+}
+
+// ------------------------------------------------------------ reductions
+
+// Per event: fixed-order sum of the row partials (this band's items) and the
+// column partials (bands from this one to the last), conversion to the raw
+// sums K, R, U, J, V, W (times exp(sigma)), and the recompute flag.
+template <bool MIX, typename ColT>
+__global__ void __launch_bounds__(256) k_reduce1(const double* __restrict__ prow, const ColT* __restrict__ pcol,
+                                                  const int2* __restrict__ band_info, const int* __restrict__ status,
+                                                  double* __restrict__ sums, double* __restrict__ sigma,
+                                                  int* __restrict__ flags, KParams kp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kp.n || status[kStData] != 0) return;
+  const int b = i / kBandRows, lr = i % kBandRows;
+  const int2 bi = band_info[b];
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (int c = 0; c < bi.y; ++c) {
+    const double* p = prow + (int64_t)(bi.x + c) * 6 * kBandRows + lr;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s[q] += p[(int64_t)q * kBandRows];
+  }
+  for (int I = b; I < kp.nb; ++I) {
+    const ColT* p = pcol + (int64_t)I * 3 * kp.n_pad + i;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) s[q] += (double)p[(int64_t)q * kp.n_pad];
+  }
+  if (MIX) {
+    s[1] /= (double)kp.Ab;
+    s[2] /= (double)kp.Bt;
+    s[4] /= (double)kp.Gs;
+    s[5] /= (double)kp.Ws;
+  }
+  const double lam = kp.cbg * s[0] + kp.cse * s[3];
+  const bool flag = !(lam >= kp.cmax * exp2(kp.flag_floor));
+#pragma unroll
+  for (int q = 0; q < 6; ++q) sums[(int64_t)i * 6 + q] = s[q];
+  sigma[i] = kp.sigma_main;
+  flags[i] = flag ? 1 : 0;
+}
+
+// Ordered list of the flagged rows (one workgroup of 1024 threads).
+__global__ void __launch_bounds__(1024) k_flaglist(const int* __restrict__ flags, int n, int* __restrict__ status,
+                                                    int* __restrict__ list) {
+  __shared__ int s_scan[1024];
+  const int tid = threadIdx.x;
+  if (status[kStData] != 0) return;
+  const int per = (n + 1023) / 1024;
+  const int lo = min(n, tid * per), hi = min(n, lo + per);
+  int cnt = 0;
+  for (int i = lo; i < hi; ++i) cnt += flags[i];
+  s_scan[tid] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = tid >= off ? s_scan[tid - off] : 0;
+    __syncthreads();
+    s_scan[tid] += v;
+    __syncthreads();
+  }
+  int pos = s_scan[tid] - cnt;
+  for (int i = lo; i < hi; ++i)
+    if (flags[i]) list[pos++] = i;
+  if (tid == 1023) status[kStFlagCount] = s_scan[1023];
+}
+
+// Exact float64 recomputation of the six row sums of each flagged row, with a
+// per-row log scale sigma = max_j log(weighted pair term): two sweeps over all
+// partners, so no term that matters can underflow.
+template <int D>
+__global__ void __launch_bounds__(256) k_fix1(const double* __restrict__ x, const double* __restrict__ t,
+                                               const int* __restrict__ status, const int* __restrict__ list,
+                                               double* __restrict__ sums, double* __restrict__ sigma, KParams kp) {
+  __shared__ double sh[256];
+  if (status[kStData] != 0) return;
+  const int cnt = status[kStFlagCount];
+  for (int f = blockIdx.x; f < cnt; f += gridDim.x) {
+    const int i = list[f];
+    double xi[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) xi[q] = x[(int64_t)i * D + q];
+    const double ti = t[i];
+    double m = -INFINITY;
+    for (int j = threadIdx.x; j < kp.n; j += 256) {
+      if (j == i) continue;
+      double r2 = 0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) { const double dx = xi[q] - x[(int64_t)j * D + q]; r2 += dx * dx; }
+      const double dt = ti - t[j];
+      if (dt != 0.0) m = fmax(m, kp.log_cbg - kp.alpha * r2 - kp.beta * dt * dt);
+      if (dt > 0.0) m = fmax(m, kp.log_cse - kp.omega * dt - kp.gamma * r2);
+    }
+    m = block_max_256(m, sh);
+    if (!(m > -INFINITY)) m = 0.0;   // no active partner: lambda is exactly 0
+    double a[6] = {0, 0, 0, 0, 0, 0};
+    for (int j = threadIdx.x; j < kp.n; j += 256) {
+      if (j == i) continue;
+      double r2 = 0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) { const double dx = xi[q] - x[(int64_t)j * D + q]; r2 += dx * dx; }
+      const double dt = ti - t[j];
+      if (dt != 0.0) {
+        const double e = exp(-kp.alpha * r2 - kp.beta * dt * dt - m);
+        a[0] += e; a[1] += e * r2; a[2] += e * dt * dt;
+      }
+      if (dt > 0.0) {
+        const double e = exp(-kp.omega * dt - kp.gamma * r2 - m);
+        a[3] += e; a[4] += e * r2; a[5] += e * dt;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double v = block_sum_256(a[q], sh);
+      if (threadIdx.x == 0) sums[(int64_t)i * 6 + q] = v;
+    }
+    if (threadIdx.x == 0) sigma[i] = m;
+  }
+}
+
+__device__ __forceinline__ double std_normal_cdf(double z) { return 0.5 * erfc(-z * 0.70710678118654752440); }
+__device__ __forceinline__ double std_normal_pdf(double z) { return 0.39894228040143267794 * exp(-0.5 * z * z); }
+
+// Per event: lambda, log lambda, compensator, log-likelihood term and the six
+// parameter-gradient terms; per-block fixed-order partials; the pass-2 factors.
+template <int D, bool MIX>
+__global__ void __launch_bounds__(256) k_final1(const double* __restrict__ t, const int* __restrict__ status,
+                                                 const double* __restrict__ dconst, const double* __restrict__ sums,
+                                                 const double* __restrict__ sigma, const int* __restrict__ flags,
+                                                 typename Traits<D, MIX>::Rec* __restrict__ rec,
+                                                 typename Traits<D, MIX>::Real* __restrict__ psrow,
+                                                 double* __restrict__ logl, double* __restrict__ blockpart, KParams kp) {
+  using Real = typename Traits<D, MIX>::Real;
+  __shared__ double sh[256];
+  if (status[kStData] != 0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (i < kp.n) {
+    const double* s = sums + (int64_t)i * 6;
+    const double sg = sigma[i];
+    const double lt = kp.cbg * s[0] + kp.cse * s[3];   // lambda * exp(-sigma)
+    const double L = log(lt) + sg;
+    const double T = dconst[0], ti = t[i];
+    const double a = (T - ti) / kp.tau_t, b = -ti / kp.tau_t;
+    const double cdf_diff = std_normal_cdf(a) - std_normal_cdf(b);
+    const double decay = exp(-kp.omega * (T - ti));
+    const double omd = -expm1(-kp.omega * (T - ti));
+    const double Lam = kp.mu0 * cdf_diff + kp.theta * omd;
+    const double dtau = -kp.mu0 / (kp.tau_t * kp.tau_t) * ((T - ti) * std_normal_pdf(a) + ti * std_normal_pdf(b));
+    const double il = 1.0 / lt;
+    v[0] = L - Lam;
+    v[1] = kp.cbg_unit * s[0] * il - cdf_diff;
+    v[2] = kp.cbg * (s[1] / (kp.tau_x * kp.tau_x * kp.tau_x) - D * s[0] / kp.tau_x) * il;
+    v[3] = kp.cbg * (s[2] / (kp.tau_t * kp.tau_t * kp.tau_t) - s[0] / kp.tau_t) * il - dtau;
+    v[4] = kp.cse_unit * s[3] * il - omd;
+    v[5] = kp.cse * (s[3] / kp.omega - s[5]) * il - kp.theta * (T - ti) * decay;
+    v[6] = kp.cse * (s[4] / (kp.h * kp.h * kp.h) - D * s[3] / kp.h) * il;
+    v[7] = lt > 0.0 ? 0.0 : 1.0;
+    logl[i] = L;
+    // pass-2 factors: 1/lambda scaled to the main pass's 2^S terms
+    const bool fl = flags[i] != 0;
+    const double pb = fl ? 0.0 : kp.cbg * kp.itx2 * il;
+    const double ps = fl ? 0.0 : kp.cse * kp.ih2 * il;
+    rec[i].v[D + 1] = (Real)pb;
+    psrow[i] = (Real)ps;
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double r = block_sum_256(v[q], sh);
+    if (threadIdx.x == 0) blockpart[(int64_t)blockIdx.x * 8 + q] = r;
+  }
+}
+
+// Sum the per-block partials in block order; out8 = [ell, 6 gradients, status].
+__global__ void __launch_bounds__(256) k_final2(const double* __restrict__ blockpart, int nblk,
+                                                 int* __restrict__ status, double* __restrict__ out8) {
+  __shared__ double sh[256];
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int bad = status[kStData];
+  if (bad == 0) {
+    for (int b = threadIdx.x; b < nblk; b += 256)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] += blockpart[(int64_t)b * 8 + q];
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = block_sum_256(v[q], sh);
+  if (threadIdx.x == 0) {
+    if (bad != 0) {
+      for (int q = 0; q < 7; ++q) out8[q] = NAN;
+      out8[7] = (double)bad;
+    } else if (v[7] > 0.0) {
+      status[kStZero] = 1;
+      out8[0] = -INFINITY;
+      for (int q = 1; q < 7; ++q) out8[q] = NAN;
+      out8[7] = -4.0;
+    } else {
+      for (int q = 0; q < 7; ++q) out8[q] = v[q];
+      out8[7] = 0.0;
+    }
+  }
+}
+
+// Location-gradient fix-up for flagged rows j: the j-side coefficient of
+// every pair (j, i), c = mu_ij/(lambda_j tau_x^2) + [t_i < t_j] xi_ji/(lambda_j h^2),
+// formed as exp(log-term - log lambda_j) in float64.
+// Sweep B (one thread per event i): sum over flagged j of c (x_j - x_i).
+template <int D>
+__global__ void __launch_bounds__(256) k_fix2b(const double* __restrict__ x, const double* __restrict__ t,
+                                                const int* __restrict__ status, const int* __restrict__ list,
+                                                const double* __restrict__ logl, double* __restrict__ gfix,
+                                                KParams kp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kp.n || status[kStData] != 0 || status[kStZero] != 0) return;
+  const int cnt = status[kStFlagCount];
+  double g[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) g[q] = 0.0;
+  double xi[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) xi[q] = x[(int64_t)i * D + q];
+  const double ti = t[i];
+  for (int f = 0; f < cnt; ++f) {
+    const int j = list[f];
+    if (j == i) continue;
+    double dx[D], r2 = 0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) { dx[q] = x[(int64_t)j * D + q] - xi[q]; r2 += dx[q] * dx[q]; }
+    const double dt = t[j] - ti;   // > 0 when j is the later event
+    const double Lj = logl[j];
+    double c = 0.0;
+    if (dt != 0.0) c += exp(kp.log_cbg - kp.alpha * r2 - kp.beta * dt * dt - Lj) * kp.itx2;
+    if (dt > 0.0) c += exp(kp.log_cse - kp.omega * dt - kp.gamma * r2 - Lj) * kp.ih2;
+#pragma unroll
+    for (int q = 0; q < D; ++q) g[q] += c * dx[q];
+  }
+#pragma unroll
+  for (int q = 0; q < D; ++q) gfix[(int64_t)i * D + q] = g[q];
+}
+
+// Sweep A (one workgroup per flagged row j): sum over all i of c (x_i - x_j),
+// added to the row's fix-up gradient.
+template <int D>
+__global__ void __launch_bounds__(256) k_fix2a(const double* __restrict__ x, const double* __restrict__ t,
+                                                const int* __restrict__ status, const int* __restrict__ list,
+                                                const double* __restrict__ logl, double* __restrict__ gfix,
+                                                KParams kp) {
+  __shared__ double sh[256];
+  if (status[kStData] != 0 || status[kStZero] != 0) return;
+  const int cnt = status[kStFlagCount];
+  for (int f = blockIdx.x; f < cnt; f += gridDim.x) {
+    const int j = list[f];
+    double xj[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) xj[q] = x[(int64_t)j * D + q];
+    const double tj = t[j], Lj = logl[j];
+    double g[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) g[q] = 0.0;
+    for (int i = threadIdx.x; i < kp.n; i += 256) {
+      if (i == j) continue;
+      double dx[D], r2 = 0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) { dx[q] = x[(int64_t)i * D + q] - xj[q]; r2 += dx[q] * dx[q]; }
+      const double dt = tj - t[i];
+      double c = 0.0;
+      if (dt != 0.0) c += exp(kp.log_cbg - kp.alpha * r2 - kp.beta * dt * dt - Lj) * kp.itx2;
+      if (dt > 0.0) c += exp(kp.log_cse - kp.omega * dt - kp.gamma * r2 - Lj) * kp.ih2;
+#pragma unroll
+      for (int q = 0; q < D; ++q) g[q] += c * dx[q];
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const double v = block_sum_256(g[q], sh);
+      if (threadIdx.x == 0) gfix[(int64_t)j * D + q] += v;
+    }
+  }
+}
+
+// grad_x = row partials + column partials + fix-up terms (fixed order).
+template <int D, typename ColT>
+__global__ void __launch_bounds__(256) k_reduce2(const double* __restrict__ prow, const ColT* __restrict__ pcol,
+                                                  const int2* __restrict__ band_info, const int* __restrict__ status,
+                                                  const double* __restrict__ gfix, double* __restrict__ grad_x,
+                                                  KParams kp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kp.n || status[kStData] != 0) return;
+  if (status[kStZero] != 0) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) grad_x[(int64_t)i * D + q] = NAN;
+    return;
+  }
+  const int b = i / kBandRows, lr = i % kBandRows;
+  const int2 bi = band_info[b];
+  double s[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) s[q] = 0.0;
+  for (int c = 0; c < bi.y; ++c) {
+    const double* p = prow + (int64_t)(bi.x + c) * D * kBandRows + lr;
+#pragma unroll
+    for (int q = 0; q < D; ++q) s[q] += p[(int64_t)q * kBandRows];
+  }
+  for (int I = b; I < kp.nb; ++I) {
+    const ColT* p = pcol + (int64_t)I * D * kp.n_pad + i;
+#pragma unroll
+    for (int q = 0; q < D; ++q) s[q] += (double)p[(int64_t)q * kp.n_pad];
+  }
+#pragma unroll
+  for (int q = 0; q < D; ++q) grad_x[(int64_t)i * D + q] = s[q] + gfix[(int64_t)i * D + q];
+}
+
+}  // namespace hawkes

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP library through the C ABI against the CPU oracle.
+
+FP64 path: 1e-10 relative on the log-likelihood, the location gradient
+(Frobenius norm) and the parameter gradient (scaled as in gpu_util.param_err).
+Mixed path: 1e-5 on the log-likelihood, 1e-4 on both gradients."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_02994_amd import workloads as W
+from tests.gpu_util import check, run_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp64", "mixed"]
+
+
+def _oracle(x, t, p):
+    st, ll, gx, gp = oracle.loglik_grad(x, t, p, threads=True)
+    assert st == 0
+    return ll, gx, gp
+
+
+SMALL = [(1, 2, 1, 0), (2, 3, 2, 0), (3, 17, 2, 1), (4, 63, 3, 0), (5, 64, 2, 2), (6, 65, 1, 0), (7, 257, 6, 3),
+         (8, 511, 2, 0), (9, 512, 2, 0), (10, 513, 8, 2), (11, 1000, 2, 4), (12, 1537, 3, 0), (13, 700, 5, 1),
+         (14, 129, 4, 0), (15, 300, 7, 0)]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("seed,n,d,ties", SMALL)
+def test_random_cases(prec, seed, n, d, ties):
+    w = W.random_case(seed, n, d, ties=ties, t_span=max(3.0, n / 40))
+    say(f"case seed={seed} n={n} d={d} ties={ties} prec={prec}")
+    ref = _oracle(w.x, w.t, w.params)
+    out = run_gpu(w.x, w.t, w.params, prec)
+    check(prec, *out, *ref, w.params, w.n, label=w.name)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("which", ["theta0", "mu_tiny"])
+def test_single_component(prec, which):
+    """theta = 0 (background only) and mu0 = 1e-9 (excitation dominates)."""
+    w = W.random_case(21, 300, 2, ties=2, t_span=6.0)
+    p = w.params.copy()
+    if which == "theta0":
+        p[3] = 0.0
+    else:
+        p[0] = 1e-9
+    say(f"case single-component {which} prec={prec}")
+    check(prec, *run_gpu(w.x, w.t, p, prec), *_oracle(w.x, w.t, p), p, w.n, label=which)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mu_zero_is_zero_rate(prec):
+    """mu0 = 0: the earliest event has no earlier partner, so its rate is 0."""
+    w = W.random_case(22, 200, 2, t_span=6.0)
+    p = w.params.copy()
+    p[0] = 0.0
+    st, ll, _, _ = oracle.loglik_grad(w.x, w.t, p)
+    assert st == oracle.ZERORATE and ll == -math.inf
+    say(f"case mu0=0 prec={prec}")
+    ll_gpu, gx, gp = run_gpu(w.x, w.t, p, prec)
+    assert ll_gpu == -math.inf and np.all(np.isnan(gx)) and np.all(np.isnan(gp))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config0(prec):
+    w = W.config0()
+    say(f"case {w.name} prec={prec}")
+    check(prec, *run_gpu(w.x, w.t, w.params, prec), *_oracle(w.x, w.t, w.params), w.params, w.n, label=w.name)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return W.config1(snapshots=3)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("snap", [0, 3])
+def test_config1_snapshots(c1, prec, snap):
+    x = c1.x if snap == 0 else c1.snapshots[snap - 1]
+    say(f"case {c1.name} snapshot={snap} prec={prec}")
+    check(prec, *run_gpu(x, c1.t, c1.params, prec), *_oracle(x, c1.t, c1.params), c1.params, c1.n,
+          label=f"{c1.name}/s{snap}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config3_d6(prec):
+    w = W.config3()
+    say(f"case {w.name} prec={prec}")
+    check(prec, *run_gpu(w.x, w.t, w.params, prec), *_oracle(w.x, w.t, w.params), w.params, w.n, label=w.name)
+
+
+@pytest.fixture(scope="module")
+def c2_ref():
+    w = W.config2()
+    say(f"oracle {w.name} (threaded) ...")
+    st, ll, _, gp = oracle.loglik_grad(w.x, w.t, w.params, threads=True, want_grad_x=False)
+    assert st == 0
+    lam, _ = oracle.rates(w.x, w.t, w.params, threads=True)
+    rng = np.random.default_rng(7)
+    rows = np.sort(np.r_[rng.choice(w.n, 400, replace=False), np.argsort(lam)[:40], 0, w.n - 1])
+    rows = np.unique(rows)
+    g_rows = oracle.grad_rows(w.x, w.t, w.params, lam, rows)
+    return w, ll, gp, rows, g_rows, lam
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config2_full_size(c2_ref, prec):
+    """N = 50,000: full log-likelihood and parameter gradient, location gradient
+    on 440 sampled rows (random plus the 40 smallest-rate rows, which exercise
+    the float64 fix-up of rows below the float32 window)."""
+    w, ll_ref, gp_ref, rows, g_rows, lam = c2_ref
+    say(f"case {w.name} prec={prec}")
+    ll, gx, gp = run_gpu(w.x, w.t, w.params, prec)
+    check(prec, ll, gx[rows], gp, ll_ref, g_rows, gp_ref, w.params, w.n, label=w.name)
+    # translation invariance holds at any size: sum of gradients vanishes
+    scale = np.abs(gx).sum(0)
+    assert np.all(np.abs(gx.sum(0)) <= (1e-12 if prec == "fp64" else 1e-6) * scale)
+
+
+def _isolated_case():
+    """Moves event 5 about 28 bandwidths away (log rate near -300 relative to
+    the pair weight: below the float32 window) and event 200 just far enough
+    that its log rate falls between -700 and -630 (below the float64 path's
+    2^-900 window, yet still positive in float64)."""
+    w = W.random_case(31, 400, 2, t_span=10.0)
+    p = np.array([0.5, 1.0, 1.0, 0.3, 1.0, 0.5])
+    d = 2
+    cmax = max(p[0] * (2 * np.pi) ** (-(d + 1) / 2) / p[1] ** d / p[2],
+               p[3] * p[4] * (2 * np.pi) ** (-d / 2) / p[5] ** d)
+    x = w.x.copy()
+    x[5] += 20.0   # both coordinates: about 28 bandwidths away
+    for off in np.arange(26.0, 30.0, 0.05):
+        x[200] = w.x[200] - off
+        lam, _ = oracle.rates(x, w.t, p)
+        rel = np.log(lam[200] / cmax) if lam[200] > 0 else -np.inf
+        if -700 < rel < -630:
+            return x, w.t, p
+    raise AssertionError("could not place the isolated event")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_isolated_events_fixup(prec):
+    """Rows far below the float32 window (and one below the float64 window) are
+    recomputed exactly by the fix-up kernels."""
+    x, t, p = _isolated_case()
+    st, ll_ref, gx_ref, gp_ref = oracle.loglik_grad(x, t, p, threads=True)
+    assert st == 0
+    lam, _ = oracle.rates(x, t, p)
+    say(f"case isolated prec={prec} min log lam {np.log(lam).min():.1f}")
+    check(prec, *run_gpu(x, t, p, prec), ll_ref, gx_ref, gp_ref, p, len(t), label="isolated")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_translation_offset_mixed_stable(prec):
+    """A large common offset must not degrade the result (float32 offsets are
+    taken from the data center)."""
+    w = W.random_case(41, 1000, 2, t_span=20.0)
+    ref = _oracle(w.x, w.t, w.params)
+    say(f"case offset prec={prec}")
+    check(prec, *run_gpu(w.x + 5.0e4, w.t + 1.0e4, w.params, prec), *_oracle(w.x + 5.0e4, w.t + 1.0e4, w.params),
+          w.params, w.n, label="offset")
+    # the oracle itself: a 5e4 offset costs ~1e-11 relative through float64
+    # rounding of the shifted coordinates, so translation holds to 1e-9 here
+    assert ref[0] == pytest.approx(_oracle(w.x + 5.0e4, w.t, w.params)[0], rel=1e-9)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_all_tied_is_zero_rate(prec):
+    x = np.random.default_rng(1).standard_normal((70, 2))
+    t = np.full(70, 1.5)
+    say(f"case all-tied prec={prec}")
+    ll, gx, gp = run_gpu(x, t, [0.5, 1, 1, 0.3, 1, 0.5], prec)
+    assert ll == -math.inf and np.all(np.isnan(gx)) and np.all(np.isnan(gp))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_deterministic_bitwise(prec):
+    w = W.random_case(51, 3000, 2, ties=3, t_span=60.0)
+    say(f"case determinism prec={prec}")
+    a = run_gpu(w.x, w.t, w.params, prec)
+    b = run_gpu(w.x, w.t, w.params, prec)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_invalid_inputs_return_status_and_leave_outputs():
+    import torch
+    from paper_2010_02994_amd import _lib, api
+    rng = np.random.default_rng(3)
+    x = torch.tensor(rng.standard_normal((100, 2)), device="cuda:0")
+    t_ok = np.sort(rng.uniform(0, 5, 100))
+    p = [0.5, 1, 1, 0.3, 1, 0.5]
+    say("case invalid inputs")
+    for bad_t, bad_x in ((t_ok[::-1].copy(), None), (t_ok - 1.0, None), (t_ok, "nan")):
+        tt = torch.tensor(bad_t, device="cuda:0")
+        xx = x.clone()
+        if bad_x == "nan":
+            xx[7, 1] = float("nan")
+        sentinel = torch.full_like(xx, 123.0)
+        with pytest.raises(_lib.HawkesError) as e:
+            api.grad(xx, tt, p, prec="mixed", out=sentinel)
+        assert e.value.status == _lib.EDATA
+        torch.cuda.synchronize()
+        assert bool((sentinel == 123.0).all())
+    for badp in ([0.5, -1, 1, 0.3, 1, 0.5], [0, 1, 1, 0, 1, 0.5], [0.5, 1, 1, 0.3, float("inf"), 0.5]):
+        with pytest.raises(_lib.HawkesError) as e:
+            api.grad(x, torch.tensor(t_ok, device="cuda:0"), badp)
+        assert e.value.status == _lib.EPARAM
