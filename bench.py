@@ -29,6 +29,8 @@ METRIC = "pair-interactions/s for Hawkes loglik+grad (FP64 vs mixed); serve p50/
 STAGES = ["prep", "pack", "pass1", "reduce1", "flaglist", "fix1", "final1", "final2", "pass2", "fix2b", "fix2a",
           "reduce2"]
 KERNEL_NAMES = {"pass1": "k_pass1", "pass2": "k_pass2"}
+PROFILED_NAMES = {("pass1", "mixed"): "hawkes::k_pass1_mixed<2>", ("pass2", "mixed"): "hawkes::k_pass2_mixed<2>",
+                  ("pass1", "fp64"): "hawkes::k_pass1<2, false>", ("pass2", "fp64"): "hawkes::k_pass2<2, false>"}
 
 # Peaks of the chip (256 CUs at 2.4 GHz).  FP32 vector: 157.3 TFLOP/s.  The
 # v_exp_f32 issue rate is 32 lanes per CU per clock (measured by the peaks
@@ -37,6 +39,33 @@ PEAK_FP32 = 157.3e12
 PEAK_FP64 = 78.6e12
 EXP_F32_PER_S = 256 * 2.4e9 * 32
 FLOP_EQ_PER_EXP = PEAK_FP32 / EXP_F32_PER_S
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hawkes_kernels.hpp", "hawkes_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2010_02994_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_prefix: str, workload: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size),
+    or None when the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hawkes_grad_c2_n50000_d2.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    if rec.get("source_sha256_16") != kernel_source_hash() or rec.get("workload") != workload:
+        return None
+    for k, v in rec["kernels"].items():
+        if k.startswith(kernel_prefix):
+            return int(v["bytes_read"] + v["bytes_written"])
+    return None
 
 
 def pass_work(d: int, which: str):
@@ -125,7 +154,8 @@ def main():
     peak = PEAK_FP32 if args.prec == "mixed" else PEAK_FP64
     roof = {"bound": "alu", "kernel": f"{KERNEL_NAMES[dom]}<D={d},{args.prec}>",
             "achieved": round(achieved / 1e12, 3), "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic(PROFILED_NAMES.get((dom, args.prec), "?"), w.name) if d == 2 else None,
             "work_per_unordered_pair": {"flops": flops, "exps": exps, "flop_eq_per_exp": FLOP_EQ_PER_EXP},
             "kernel_ms": round(pass_ms[dom], 4)}
     # whole-path roofline: both passes' algorithmic work over the full step time

@@ -89,7 +89,76 @@ static double run(const char* name, int ops_per_chain_step, int grid, float* o, 
   return rate;
 }
 
-int main() {
+// LDS accumulate throughput: one wave instruction per step, 64 distinct
+// addresses (XOR schedule).  KIND 0: ds_add_f32, 1: ds_add_f64,
+// 2: read-modify-write of a float4 (ds_read_b128, 3 adds, ds_write_b128).
+template <int KIND>
+__global__ void __launch_bounds__(256) k_lds(float* out, float val, int iters) {
+  __shared__ float sf[4][256];
+  __shared__ double sd[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < 4 * 256; i += 256) (&sf[0][0])[i] = 0.f;
+  for (int i = threadIdx.x; i < 4 * 64; i += 256) (&sd[0][0])[i] = 0.0;
+  __syncthreads();
+  const float v = val + 1e-3f * lane;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll 8
+    for (int k = 0; k < 64; ++k) {
+      const int c = lane ^ k;
+      if constexpr (KIND == 0) atomicAdd(&sf[w][c], v);
+      else if constexpr (KIND == 1) atomicAdd(&sd[w][c], (double)v);
+      else {
+        float4* p = reinterpret_cast<float4*>(&sf[w][0]) + c;
+        float4 q = *p; q.x += v; q.y += v; q.z += v; *p = q;
+      }
+    }
+  }
+  __syncthreads();
+  out[blockIdx.x * 256 + threadIdx.x] = sf[w][lane] + (float)sd[w][lane];
+}
+
+template <int KIND>
+static void lds_run(const char* name, float* o, int grid) {
+  hipEvent_t a, b; CHECK(hipEventCreate(&a)); CHECK(hipEventCreate(&b));
+  const int iters = 100;
+  k_lds<KIND><<<grid, 256>>>(o, 1.f, 5);
+  CHECK(hipDeviceSynchronize());
+  CHECK(hipEventRecord(a));
+  k_lds<KIND><<<grid, 256>>>(o, 1.f, iters);
+  CHECK(hipEventRecord(b)); CHECK(hipEventSynchronize(b));
+  float ms = 0.f; CHECK(hipEventElapsedTime(&ms, a, b));
+  const double wave_steps_per_cu = (double)grid * 4 * iters * 64 / 256.0;
+  std::printf("{\"op\": \"%s\", \"ns_per_wave_instruction_per_cu\": %.3f}\n", name, ms * 1e6 / wave_steps_per_cu);
+  CHECK(hipEventDestroy(a)); CHECK(hipEventDestroy(b));
+}
+
+// Plain streaming copy of a known byte count: the reference against which the
+// FETCH_SIZE / WRITE_SIZE hardware counters are scaled.
+__global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src, float4* __restrict__ dst, size_t n4) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+static int copy_mode(size_t mib) {
+  const size_t bytes = mib << 20, n4 = bytes / 16;
+  float4 *a, *b;
+  CHECK(hipMalloc(&a, bytes)); CHECK(hipMalloc(&b, bytes));
+  CHECK(hipMemset(a, 0, bytes));
+  hipEvent_t e0, e1; CHECK(hipEventCreate(&e0)); CHECK(hipEventCreate(&e1));
+  for (int r = 0; r < 3; ++r) {
+    CHECK(hipEventRecord(e0));
+    k_copy<<<4096, 256>>>(a, b, n4);
+    CHECK(hipEventRecord(e1)); CHECK(hipEventSynchronize(e1));
+    float ms = 0.f; CHECK(hipEventElapsedTime(&ms, e0, e1));
+    std::printf("{\"op\": \"copy\", \"bytes_read\": %zu, \"bytes_written\": %zu, \"ms\": %.4f, \"GB_per_s\": %.1f}\n",
+                bytes, bytes, ms, 2.0 * bytes / (ms * 1e-3) / 1e9);
+  }
+  CHECK(hipFree(a)); CHECK(hipFree(b));
+  return 0;
+}
+
+int main(int argc, char** argv) {
+  if (argc > 1 && std::strcmp(argv[1], "copy") == 0) return copy_mode(argc > 2 ? (size_t)std::atoll(argv[2]) : 256);
   hipDeviceProp_t p; CHECK(hipGetDeviceProperties(&p, 0));
   std::printf("{\"device\": \"%s\", \"gcn\": \"%s\", \"cus\": %d, \"clock_khz\": %d}\n",
               p.name, p.gcnArchName, p.multiProcessorCount, p.clockRate);
@@ -106,6 +175,9 @@ int main() {
   run<5>("v_cvt_f64_f32+v_cvt_f32_f64", 2, grid, o, o64);
   run<7>("v_sub_u32", 1, grid, o, o64);
   run<6>("exp+3fma (instructions)", 4, grid, o, o64);
+  lds_run<0>("ds_add_f32", o, grid);
+  lds_run<1>("ds_add_f64", o, grid);
+  lds_run<2>("ds_read_b128+3 v_add_f32+ds_write_b128", o, grid);
   CHECK(hipFree(o)); CHECK(hipFree(o64));
   return 0;
 }
