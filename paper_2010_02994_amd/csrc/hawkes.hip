@@ -9,6 +9,7 @@
 
 #include "../../include/hawkes.h"
 #include "hawkes_common.hpp"
+#include "hawkes_internal.hpp"
 #include "hawkes_kernels.hpp"
 
 namespace hawkes {
@@ -19,14 +20,6 @@ constexpr double kFloorFp64 = -900.0;       // flag when lambda < cmax * 2^-900
 constexpr int kFixGrid = 256;
 constexpr int kTargetItems = 2048;
 constexpr int kNumStages = 12;
-
-struct Layout {
-  int64_t n = 0;
-  int d = 0, mixed = 0;
-  int nb = 0, n_pad = 0, L = 1, items = 0, nblk = 0;
-  size_t off_status, off_dconst, off_out8, off_items, off_band, off_rec, off_first, off_ps, off_prow, off_pcol,
-      off_sums, off_sigma, off_flags, off_list, off_logl, off_bpart, off_gfix, total;
-};
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -41,7 +34,7 @@ static int tiles_per_item(int64_t n) {
   return (int)std::max<int64_t>(1, (tiles + kTargetItems - 1) / kTargetItems);
 }
 
-static bool make_layout(int64_t n, int d, int prec, Layout& Lo) {
+bool make_layout(int64_t n, int d, int prec, Layout& Lo) {
   if (n < 2 || n > (int64_t(1) << 30) || d < 1 || d > kMaxD || (prec != HAWKES_FP64 && prec != HAWKES_MIXED))
     return false;
   Lo.n = n;
@@ -55,16 +48,17 @@ static bool make_layout(int64_t n, int d, int prec, Layout& Lo) {
     const int64_t nt = (std::min<int64_t>(n, (int64_t)(b + 1) * kBandRows) + kTile - 1) / kTile;
     Lo.items += (int)((nt + Lo.L - 1) / Lo.L);
   }
-  Lo.nblk = (int)((n + 255) / 256);
+  Lo.nblk = (int)((n + kEvBlock - 1) / kEvBlock);
   const size_t real = Lo.mixed ? 4 : 8;
   const int rw = Lo.mixed ? ((d + 2 + 3) / 4) * 4 : ((d + 2 + 1) / 2) * 2;
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+  Lo.off_desc = take(sizeof(ReqDesc));
   Lo.off_status = take(sizeof(int) * kStSlots);
   Lo.off_dconst = take(sizeof(double) * 16);
   Lo.off_out8 = take(sizeof(double) * 8);
-  Lo.off_items = take(sizeof(int2) * (size_t)Lo.items);
-  Lo.off_band = take(sizeof(int2) * (size_t)Lo.nb);
+  Lo.off_items = take(sizeof(IPair) * (size_t)Lo.items);
+  Lo.off_band = take(sizeof(IPair) * (size_t)Lo.nb);
   Lo.off_rec = take(real * rw * (size_t)Lo.n_pad);
   Lo.off_first = take(sizeof(int) * (size_t)Lo.n_pad);
   Lo.off_ps = take(real * (size_t)Lo.n_pad);
@@ -74,14 +68,18 @@ static bool make_layout(int64_t n, int d, int prec, Layout& Lo) {
   Lo.off_sigma = take(sizeof(double) * (size_t)n);
   Lo.off_flags = take(sizeof(int) * (size_t)n);
   Lo.off_list = take(sizeof(int) * (size_t)n);
+  Lo.off_listpos = take(sizeof(int) * (size_t)n);
+  Lo.off_bcount = take(sizeof(int) * (size_t)Lo.nblk);
+  Lo.off_bstage = take(sizeof(int) * (size_t)Lo.nblk * kEvBlock);
   Lo.off_logl = take(sizeof(double) * (size_t)n);
   Lo.off_bpart = take(sizeof(double) * 8 * (size_t)Lo.nblk);
   Lo.off_gfix = take(sizeof(double) * (size_t)d * n);
+  Lo.off_fixpart = take(sizeof(double) * 8 * kFixSeg * (size_t)n);
   Lo.total = o;
   return true;
 }
 
-static bool valid_params(const hawkes_params_t* p) {
+bool valid_params(const hawkes_params_t* p) {
   const double v[6] = {p->mu, p->h, p->tau, p->theta, p->omega, p->xi};
   for (double a : v)
     if (!std::isfinite(a)) return false;
@@ -90,7 +88,7 @@ static bool valid_params(const hawkes_params_t* p) {
   return true;
 }
 
-static KParams make_kparams(const Layout& Lo, const hawkes_params_t* p) {
+KParams make_kparams(const Layout& Lo, const hawkes_params_t* p) {
   KParams k;
   std::memset(&k, 0, sizeof(k));
   const int D = Lo.d;
@@ -102,6 +100,7 @@ static KParams make_kparams(const Layout& Lo, const hawkes_params_t* p) {
   k.L = Lo.L;
   k.items = Lo.items;
   k.d = D;
+  k.nblk = Lo.nblk;
   k.mu0 = p->mu;
   k.tau_x = p->h;
   k.tau_t = p->tau;
@@ -136,6 +135,39 @@ static T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
+// Per-request descriptor: constants, inputs and outputs, workspace pieces.
+ReqDesc make_desc(const Layout& Lo, const KParams& kp, const double* x, const double* t, void* ws, double* out8,
+                  double* grad_x) {
+  ReqDesc r;
+  std::memset(&r, 0, sizeof(r));
+  r.kp = kp;
+  r.x = x;
+  r.t = t;
+  r.grad_x = grad_x;
+  r.out8 = out8;
+  r.status = at<int>(ws, Lo.off_status);
+  r.dconst = at<double>(ws, Lo.off_dconst);
+  r.items = at<IPair>(ws, Lo.off_items);
+  r.band = at<IPair>(ws, Lo.off_band);
+  r.rec = at<void>(ws, Lo.off_rec);
+  r.first = at<int>(ws, Lo.off_first);
+  r.ps = at<void>(ws, Lo.off_ps);
+  r.prow = at<double>(ws, Lo.off_prow);
+  r.pcol = at<void>(ws, Lo.off_pcol);
+  r.sums = at<double>(ws, Lo.off_sums);
+  r.sigma = at<double>(ws, Lo.off_sigma);
+  r.flags = at<int>(ws, Lo.off_flags);
+  r.list = at<int>(ws, Lo.off_list);
+  r.listpos = at<int>(ws, Lo.off_listpos);
+  r.bcount = at<int>(ws, Lo.off_bcount);
+  r.bstage = at<int>(ws, Lo.off_bstage);
+  r.logl = at<double>(ws, Lo.off_logl);
+  r.bpart = at<double>(ws, Lo.off_bpart);
+  r.gfix = at<double>(ws, Lo.off_gfix);
+  r.fixpart = at<double>(ws, Lo.off_fixpart);
+  return r;
+}
+
 // Optional per-stage timing (hawkes_grad_timed): events recorded before each
 // launch on the call's stream.
 struct StageTimer {
@@ -151,76 +183,77 @@ static inline void mark(hipStream_t s, int stage) {
   }
 }
 
+// The twelve phases over every request of a batch (all with the same D and
+// precision).  reqs: device array of descriptors; totals: grid sizes.
 template <int D, bool MIX>
-static void launch_all(const Layout& Lo, const KParams& kp, const double* x, const double* t, void* ws,
-                       hipStream_t s, double* out8, double* grad_x) {
-  using Tr = Traits<D, MIX>;
-  using Rec = typename Tr::Rec;
-  using Real = typename Tr::Real;
-  using ColT = typename Tr::ColT;
-  int* status = at<int>(ws, Lo.off_status);
-  double* dconst = at<double>(ws, Lo.off_dconst);
-  int2* items = at<int2>(ws, Lo.off_items);
-  int2* band = at<int2>(ws, Lo.off_band);
-  Rec* rec = at<Rec>(ws, Lo.off_rec);
-  int* first = at<int>(ws, Lo.off_first);
-  Real* ps = at<Real>(ws, Lo.off_ps);
-  double* prow = at<double>(ws, Lo.off_prow);
-  ColT* pcol = at<ColT>(ws, Lo.off_pcol);
-  double* sums = at<double>(ws, Lo.off_sums);
-  double* sigma = at<double>(ws, Lo.off_sigma);
-  int* flags = at<int>(ws, Lo.off_flags);
-  int* list = at<int>(ws, Lo.off_list);
-  double* logl = at<double>(ws, Lo.off_logl);
-  double* bpart = at<double>(ws, Lo.off_bpart);
-  double* gfix = at<double>(ws, Lo.off_gfix);
-  const int n = (int)Lo.n;
-  const int g_ev = (n + 255) / 256;
-
+static void launch_phases(const ReqDesc* reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s) {
   mark(s, 0);
-  k_prep<D><<<1, 1024, 0, s>>>(x, t, n, Lo.nb, Lo.L, status, dconst, items, band);
+  k_prep<D><<<nreq, 1024, 0, s>>>(reqs);
   mark(s, 1);
-  k_pack<D, MIX><<<Lo.n_pad / 256, 256, 0, s>>>(x, t, n, Lo.n_pad, status, dconst, rec, first, ps);
+  k_pack<D, MIX><<<g.pad_blocks, kEvBlock, 0, s>>>(reqs, nreq);
   mark(s, 2);
-  if constexpr (MIX) k_pass1_mixed<D><<<Lo.items, kThreads, 0, s>>>(rec, first, items, status, prow, pcol, kp);
-  else k_pass1<D, MIX><<<Lo.items, kThreads, 0, s>>>(rec, first, items, status, prow, pcol, kp);
+  if constexpr (MIX) k_pass1_mixed<D><<<g.items, kThreads, 0, s>>>(reqs, nreq);
+  else k_pass1<D, MIX><<<g.items, kThreads, 0, s>>>(reqs, nreq);
   mark(s, 3);
-  k_reduce1<MIX, ColT><<<g_ev, 256, 0, s>>>(prow, pcol, band, status, sums, sigma, flags, kp);
+  k_reduce1<MIX><<<g.ev_blocks, kEvBlock, 0, s>>>(reqs, nreq);
   mark(s, 4);
-  k_flaglist<<<1, 1024, 0, s>>>(flags, n, status, list);
+  k_flaglist<<<nreq, 1024, 0, s>>>(reqs);
   mark(s, 5);
-  k_fix1<D><<<kFixGrid, 256, 0, s>>>(x, t, status, list, sums, sigma, kp);
+  k_fix1<D><<<dim3(kFixGrid, nreq), 256, 0, s>>>(reqs);
   mark(s, 6);
-  k_final1<D, MIX><<<Lo.nblk, 256, 0, s>>>(t, status, dconst, sums, sigma, flags, rec, ps, logl, bpart, kp);
+  k_final1<D, MIX><<<g.ev_blocks, kEvBlock, 0, s>>>(reqs, nreq);
   mark(s, 7);
-  k_final2<<<1, 256, 0, s>>>(bpart, Lo.nblk, status, out8);
+  k_final2<<<nreq, 256, 0, s>>>(reqs);
   mark(s, 8);
-  if (grad_x) {
-    if constexpr (MIX) k_pass2_mixed<D><<<Lo.items, kThreads, 0, s>>>(rec, first, items, status, ps, prow, pcol, kp);
-    else k_pass2<D, MIX><<<Lo.items, kThreads, 0, s>>>(rec, first, items, status, ps, prow, pcol, kp);
+  if (grad) {
+    if constexpr (MIX) k_pass2_mixed<D><<<g.items, kThreads, 0, s>>>(reqs, nreq);
+    else k_pass2<D, MIX><<<g.items, kThreads, 0, s>>>(reqs, nreq);
     mark(s, 9);
-    k_fix2b<D><<<g_ev, 256, 0, s>>>(x, t, status, list, logl, gfix, kp);
+    k_fix2b<D><<<g.ev_blocks, kEvBlock, 0, s>>>(reqs, nreq);
     mark(s, 10);
-    k_fix2a<D><<<kFixGrid, 256, 0, s>>>(x, t, status, list, logl, gfix, kp);
+    k_fix2a<D><<<dim3(kFixGrid, nreq), 256, 0, s>>>(reqs);
     mark(s, 11);
-    k_reduce2<D, ColT><<<g_ev, 256, 0, s>>>(prow, pcol, band, status, gfix, grad_x, kp);
+    k_reduce2<D, MIX><<<g.ev_blocks, kEvBlock, 0, s>>>(reqs, nreq);
     mark(s, 12);
   }
 }
 
 template <bool MIX>
-static void dispatch_d(int d, const Layout& Lo, const KParams& kp, const double* x, const double* t, void* ws,
-                       hipStream_t s, double* out8, double* grad_x) {
+static void dispatch_d(int d, const ReqDesc* reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s) {
   switch (d) {
-    case 1: launch_all<1, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
-    case 2: launch_all<2, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
-    case 3: launch_all<3, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
-    case 4: launch_all<4, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
-    case 5: launch_all<5, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
-    case 6: launch_all<6, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
-    case 7: launch_all<7, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
-    case 8: launch_all<8, MIX>(Lo, kp, x, t, ws, s, out8, grad_x); break;
+    case 1: launch_phases<1, MIX>(reqs, nreq, g, grad, s); break;
+    case 2: launch_phases<2, MIX>(reqs, nreq, g, grad, s); break;
+    case 3: launch_phases<3, MIX>(reqs, nreq, g, grad, s); break;
+    case 4: launch_phases<4, MIX>(reqs, nreq, g, grad, s); break;
+    case 5: launch_phases<5, MIX>(reqs, nreq, g, grad, s); break;
+    case 6: launch_phases<6, MIX>(reqs, nreq, g, grad, s); break;
+    case 7: launch_phases<7, MIX>(reqs, nreq, g, grad, s); break;
+    case 8: launch_phases<8, MIX>(reqs, nreq, g, grad, s); break;
   }
+}
+
+// Enqueue a batch whose descriptors already sit in device memory (block
+// offsets filled in).  Returns HAWKES_EDEVICE if a launch failed.
+int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const BatchGrid& g, bool grad,
+                 hipStream_t s) {
+  (void)hipGetLastError();
+  if (mixed) dispatch_d<true>(d, dev_reqs, nreq, g, grad, s);
+  else dispatch_d<false>(d, dev_reqs, nreq, g, grad, s);
+  return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+}
+
+// Fill the block offsets of descriptors [0, nreq) and return the grid sizes.
+BatchGrid assign_blocks(ReqDesc* descs, int nreq) {
+  BatchGrid g{0, 0, 0};
+  for (int r = 0; r < nreq; ++r) {
+    descs[r].blk_items = g.items;
+    descs[r].blk_ev = g.ev_blocks;
+    descs[r].blk_pad = g.pad_blocks;
+    g.items += descs[r].kp.items;
+    g.ev_blocks += descs[r].kp.nblk;
+    g.pad_blocks += descs[r].kp.n_pad / kEvBlock;
+  }
+  return g;
 }
 
 // Host-side checks shared by every entry point.
@@ -241,10 +274,13 @@ int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_p
   if (!out8) return HAWKES_EINVAL;
   const KParams kp = make_kparams(Lo, p);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  ReqDesc desc = make_desc(Lo, kp, x, t, ws, out8, grad_x);
+  const BatchGrid g = assign_blocks(&desc, 1);
+  ReqDesc* dev = at<ReqDesc>(ws, Lo.off_desc);
   (void)hipGetLastError();
-  if (Lo.mixed) dispatch_d<true>(d, Lo, kp, x, t, ws, s, out8, grad_x);
-  else dispatch_d<false>(d, Lo, kp, x, t, ws, s, out8, grad_x);
-  return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+  k_setdesc<<<1, 64, 0, s>>>(desc, dev);
+  if (hipGetLastError() != hipSuccess) return HAWKES_EDEVICE;
+  return launch_batch(d, Lo.mixed, dev, 1, g, grad_x != nullptr, s);
 }
 
 static int run_sync(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,

@@ -11,11 +11,18 @@ constexpr int kRowsPerLane = 2;         // rows each lane owns in the pair passe
 constexpr int kBandRows = kThreads * kRowsPerLane;  // rows per band (512)
 constexpr int kTile = 64;               // columns per tile (one wave width)
 constexpr int kMaxD = 8;
+constexpr int kFixSeg = 8;              // partner segments per flagged row in the fix-up kernels
+constexpr int kEvBlock = 256;           // events per block of the per-event kernels
 
-// Status words kept in the workspace.
+// Plain pairs and 16-byte chunks (the HIP vector types cannot be used through
+// address-space-qualified pointers).
+struct IPair { int x, y; };
+struct alignas(16) Chunk16 { unsigned a, b, c, d; };
+
+// Status words kept in each request's workspace.
 enum StatusSlot { kStData = 0, kStZero = 1, kStFlagCount = 2, kStSlots = 16 };
 
-// Host-computed constants of one evaluation, passed to kernels by value.
+// Constants of one evaluation (host-computed from the parameters and sizes).
 struct KParams {
   int n;          // events
   int n_pad;      // NB * kBandRows
@@ -23,6 +30,8 @@ struct KParams {
   int L;          // column tiles per work item
   int items;      // work items of a pair pass
   int d;
+  int nblk;       // ceil(n / kEvBlock)
+  int mixed;
   // model parameters (paper symbols)
   double mu0, tau_x, tau_t, theta, omega, h;
   double cbg, cse;            // weighted pair constants
@@ -36,7 +45,40 @@ struct KParams {
   float Ab, Bt, Gs, Ws, S;    // log2(e)/(2 tau_x^2), log2(e)/(2 tau_t^2), log2(e)/(2 h^2), log2(e) omega, S
   double sigma_main;          // natural log of the scale the main pass sums carry (-S ln 2, or 0)
   double flag_floor;          // a row is recomputed when lambda~ < cmax * 2^flag_floor
-  int mixed;
+};
+
+// One request of a launch: its constants, its inputs and outputs, the pieces
+// of its workspace, and where its blocks start in each batched grid.
+struct ReqDesc {
+  KParams kp;
+  const double* x;
+  const double* t;
+  double* grad_x;   // null: rate pass and finalize only
+  double* out8;     // [loglik, 6 parameter gradients, status]
+  int* status;
+  double* dconst;
+  IPair* items;
+  IPair* band;
+  void* rec;
+  int* first;
+  void* ps;
+  double* prow;
+  void* pcol;
+  double* sums;
+  double* sigma;
+  int* flags;
+  int* list;
+  int* listpos;
+  int* bcount;
+  int* bstage;
+  double* logl;
+  double* bpart;
+  double* gfix;
+  double* fixpart;
+  int blk_items;    // first block of this request in a pair-pass launch
+  int blk_ev;       // first block in a per-event launch (kEvBlock events per block)
+  int blk_pad;      // first block in the pack launch (n_pad / kEvBlock blocks)
+  int pad_;
 };
 
 }  // namespace hawkes

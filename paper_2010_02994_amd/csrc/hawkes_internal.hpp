@@ -1,0 +1,37 @@
+// Internal interface between the evaluation entry points and the serving
+// runtime of libhawkes (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/hawkes.h"
+#include "hawkes_common.hpp"
+
+namespace hawkes {
+
+struct Layout {
+  int64_t n = 0;
+  int d = 0, mixed = 0;
+  int nb = 0, n_pad = 0, L = 1, items = 0, nblk = 0;
+  size_t off_desc, off_status, off_dconst, off_out8, off_items, off_band, off_rec, off_first, off_ps, off_prow,
+      off_pcol, off_sums, off_sigma, off_flags, off_list, off_listpos, off_bcount, off_bstage, off_logl, off_bpart,
+      off_gfix, off_fixpart, total;
+};
+
+struct BatchGrid {
+  int items;       // blocks of a pair-pass launch
+  int ev_blocks;   // blocks of a per-event launch
+  int pad_blocks;  // blocks of the pack launch
+};
+
+bool make_layout(int64_t n, int d, int prec, Layout& Lo);
+bool valid_params(const hawkes_params_t* p);
+KParams make_kparams(const Layout& Lo, const hawkes_params_t* p);
+ReqDesc make_desc(const Layout& Lo, const KParams& kp, const double* x, const double* t, void* ws, double* out8,
+                  double* grad_x);
+BatchGrid assign_blocks(ReqDesc* descs, int nreq);
+int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s);
+
+}  // namespace hawkes

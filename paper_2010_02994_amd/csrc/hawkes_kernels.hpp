@@ -18,6 +18,8 @@
 // Rows whose rate sits below the shifted window are recomputed in float64 by
 // the fix-up kernels (k_fix1, k_fix2a/b), so no event loses range.
 #pragma once
+#include <type_traits>
+
 #include "hawkes_common.hpp"
 
 namespace hawkes {
@@ -69,41 +71,78 @@ __device__ __forceinline__ double block_max_256(double v, double* sh) {
   return r;
 }
 
+// Pointers taken from a request descriptor are generic; casting them to the
+// global address space lets the compiler emit global (not flat) memory
+// instructions with scalar base addresses.
+#define HK_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ HK_GLOBAL T* glb(T* p) {
+  return (HK_GLOBAL T*)p;
+}
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Which request of a batched launch owns block `blk`: the last request whose
+// first block (offsets are non-decreasing) is <= blk.  kind 0: pair-pass
+// items, 1: per-event blocks, 2: pack blocks.
+__device__ __forceinline__ int find_req(const ReqDesc* __restrict__ reqs, int nreq, int blk, int kind) {
+  if (nreq == 1) return 0;
+  int lo = 0, hi = nreq - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int b = kind == 0 ? reqs[mid].blk_items : (kind == 1 ? reqs[mid].blk_ev : reqs[mid].blk_pad);
+    if (b <= blk) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // ------------------------------------------------------------ prepare / pack
 
-// One workgroup of 1024 threads: validates the data, finds the data center
-// (mixed path), t_N, and writes the work-item table of the pair passes.
-// Items run band-major from the last (longest) band to the first.
+// One workgroup of 1024 threads per request: validates the data, finds the
+// data center (mixed path) and t_N, and writes the work-item table of the
+// pair passes.  Items run band-major from the last (longest) band to the first.
 template <int D>
-__global__ void __launch_bounds__(1024) k_prep(const double* __restrict__ x, const double* __restrict__ t, int n,
-                                                int nb, int L, int* __restrict__ status,
-                                                double* __restrict__ dconst, int2* __restrict__ items,
-                                                int2* __restrict__ band_info) {
-  __shared__ double s_min[kMaxD + 1][32], s_max[kMaxD + 1][32];
-  __shared__ int s_bad[32];
+__global__ void __launch_bounds__(1024) k_prep(const ReqDesc* __restrict__ reqs) {
+  const ReqDesc& rq = reqs[blockIdx.x];
+  const auto x = glb(rq.x);
+  const auto t = glb(rq.t);
+  const int n = rq.kp.n, nb = rq.kp.nb, L = rq.kp.L;
+  __shared__ double s_min[kMaxD + 1][16], s_max[kMaxD + 1][16];
+  __shared__ int s_bad[16];
   __shared__ int s_scan[1024];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  double mn[kMaxD + 1], mx[kMaxD + 1];
+  double mn[D + 1], mx[D + 1];
 #pragma unroll
-  for (int k = 0; k <= kMaxD; ++k) { mn[k] = INFINITY; mx[k] = -INFINITY; }
+  for (int k = 0; k <= D; ++k) { mn[k] = INFINITY; mx[k] = -INFINITY; }
   int bad = 0;
-  for (int i = tid; i < n; i += 1024) {
-    const double ti = t[i];
-    if (!isfinite(ti) || ti < 0.0) bad = 1;
-    if (i > 0 && !(ti >= t[i - 1])) bad = 1;
-    mn[kMaxD] = fmin(mn[kMaxD], ti);
-    mx[kMaxD] = fmax(mx[kMaxD], ti);
+  // four independent loads in flight per thread and iteration
+  for (int i0 = tid; i0 < n; i0 += 4 * 1024) {
+    double tv[4], tp[4];
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const double v = x[(int64_t)i * D + k];
-      if (!isfinite(v)) bad = 1;
-      mn[k] = fmin(mn[k], v);
-      mx[k] = fmax(mx[k], v);
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * 1024;
+      tv[u] = i < n ? t[i] : 0.0;
+      tp[u] = (i < n && i > 0) ? t[i - 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * 1024;
+      if (i < n) {
+        if (!isfinite(tv[u]) || tv[u] < 0.0) bad = 1;
+        if (i > 0 && !(tv[u] >= tp[u])) bad = 1;
+        mn[D] = fmin(mn[D], tv[u]);
+        mx[D] = fmax(mx[D], tv[u]);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const double v = x[(int64_t)i * D + k];
+          if (!isfinite(v)) bad = 1;
+          mn[k] = fmin(mn[k], v);
+          mx[k] = fmax(mx[k], v);
+        }
+      }
     }
   }
-  // wave reductions, then across the 16 waves in fixed order
 #pragma unroll
-  for (int k = 0; k <= kMaxD; ++k) {
+  for (int k = 0; k <= D; ++k) {
     for (int off = 32; off > 0; off >>= 1) {
       mn[k] = fmin(mn[k], __shfl_xor(mn[k], off));
       mx[k] = fmax(mx[k], __shfl_xor(mx[k], off));
@@ -111,30 +150,31 @@ __global__ void __launch_bounds__(1024) k_prep(const double* __restrict__ x, con
   }
   for (int off = 32; off > 0; off >>= 1) bad |= __shfl_xor(bad, off);
   if (lane == 0) {
-    for (int k = 0; k <= kMaxD; ++k) { s_min[k][w] = mn[k]; s_max[k][w] = mx[k]; }
+#pragma unroll
+    for (int k = 0; k <= D; ++k) { s_min[k][w] = mn[k]; s_max[k][w] = mx[k]; }
     s_bad[w] = bad;
   }
   __syncthreads();
   if (tid == 0) {
     int b = 0;
-    double a[kMaxD + 1], z[kMaxD + 1];
-    for (int k = 0; k <= kMaxD; ++k) { a[k] = INFINITY; z[k] = -INFINITY; }
+    double a[D + 1], z[D + 1];
+    for (int k = 0; k <= D; ++k) { a[k] = INFINITY; z[k] = -INFINITY; }
     for (int ww = 0; ww < 16; ++ww) {
       b |= s_bad[ww];
-      for (int k = 0; k <= kMaxD; ++k) { a[k] = fmin(a[k], s_min[k][ww]); z[k] = fmax(z[k], s_max[k][ww]); }
+      for (int k = 0; k <= D; ++k) { a[k] = fmin(a[k], s_min[k][ww]); z[k] = fmax(z[k], s_max[k][ww]); }
     }
-    status[kStData] = b ? -3 : 0;
-    status[kStZero] = 0;
-    status[kStFlagCount] = 0;
-    dconst[0] = t[n - 1];                       // t_N (largest time for sorted input)
-    for (int k = 0; k < D; ++k) dconst[1 + k] = 0.5 * (a[k] + z[k]);
-    dconst[1 + kMaxD] = 0.5 * (a[kMaxD] + z[kMaxD]);
+    glb(rq.status)[kStData] = b ? -3 : 0;
+    glb(rq.status)[kStZero] = 0;
+    glb(rq.status)[kStFlagCount] = 0;
+    glb(rq.dconst)[0] = t[n - 1];                       // t_N (largest time for sorted input)
+    for (int k = 0; k < D; ++k) glb(rq.dconst)[1 + k] = 0.5 * (a[k] + z[k]);
+    glb(rq.dconst)[1 + kMaxD] = 0.5 * (a[D] + z[D]);
   }
   // work items: chunks of band b = ceil(ntiles_b / L), bands in descending order
   const int per = (nb + 1023) / 1024;
   int local = 0;
   for (int q = 0; q < per; ++q) {
-    const int pos = tid * per + q;      // position in descending band order
+    const int pos = tid * per + q;
     if (pos < nb) {
       const int b = nb - 1 - pos;
       const int row_end = min(n, (b + 1) * kBandRows);
@@ -158,8 +198,9 @@ __global__ void __launch_bounds__(1024) k_prep(const double* __restrict__ x, con
       const int row_end = min(n, (b + 1) * kBandRows);
       const int nt = (row_end + kTile - 1) / kTile;
       const int ch = (nt + L - 1) / L;
-      band_info[b] = make_int2(base, ch);
-      for (int c = 0; c < ch; ++c) items[base + c] = make_int2(b, c);
+      glb(rq.band)[b].x = base;
+      glb(rq.band)[b].y = ch;
+      for (int c = 0; c < ch; ++c) { glb(rq.items)[base + c].x = b; glb(rq.items)[base + c].y = c; }
       base += ch;
     }
   }
@@ -169,27 +210,27 @@ __global__ void __launch_bounds__(1024) k_prep(const double* __restrict__ x, con
 // (sorted input), so for j < i: t_j < t_i  <=>  j < first[i].  Padded rows get
 // first = 0, which makes every pair with them inactive.
 template <int D, bool MIX>
-__global__ void __launch_bounds__(256) k_pack(const double* __restrict__ x, const double* __restrict__ t, int n,
-                                               int n_pad, const int* __restrict__ status,
-                                               const double* __restrict__ dconst,
-                                               typename Traits<D, MIX>::Rec* __restrict__ rec, int* __restrict__ first,
-                                               typename Traits<D, MIX>::Real* __restrict__ psrow) {
+__global__ void __launch_bounds__(kEvBlock) k_pack(const ReqDesc* __restrict__ reqs, int nreq) {
   using Tr = Traits<D, MIX>;
   using Real = typename Tr::Real;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_pad || status[kStData] != 0) return;
-  typename Tr::Rec r;
+  const int r = find_req(reqs, nreq, blockIdx.x, 2);
+  const ReqDesc& rq = reqs[r];
+  const int i = (blockIdx.x - rq.blk_pad) * kEvBlock + threadIdx.x;
+  const int n = rq.kp.n;
+  if (i >= rq.kp.n_pad || glb(rq.status)[kStData] != 0) return;
+  const auto t = glb(rq.t);
+  typename Tr::Rec rr;
 #pragma unroll
-  for (int k = 0; k < Tr::RW; ++k) r.v[k] = Real(0);
+  for (int k = 0; k < Tr::RW; ++k) rr.v[k] = Real(0);
   int f = 0;
   if (i < n) {
     const double ti = t[i];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const double v = x[(int64_t)i * D + k];
-      r.v[k] = MIX ? Real(v - dconst[1 + k]) : Real(v);
+      const double v = glb(rq.x)[(int64_t)i * D + k];
+      rr.v[k] = MIX ? Real(v - glb(rq.dconst)[1 + k]) : Real(v);
     }
-    r.v[D] = MIX ? Real(ti - dconst[1 + kMaxD]) : Real(ti);
+    rr.v[D] = MIX ? Real(ti - glb(rq.dconst)[1 + kMaxD]) : Real(ti);
     int lo = 0, hi = i;   // lower_bound of ti in t[0..i]
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
@@ -197,9 +238,13 @@ __global__ void __launch_bounds__(256) k_pack(const double* __restrict__ x, cons
     }
     f = lo;
   }
-  rec[i] = r;
-  first[i] = f;
-  psrow[i] = Real(0);
+  {
+    const auto dst = glb(static_cast<typename Tr::Rec*>(rq.rec));
+#pragma unroll
+    for (int q = 0; q < Tr::RW; ++q) dst[i].v[q] = rr.v[q];
+  }
+  glb(rq.first)[i] = f;
+  glb(static_cast<Real*>(rq.ps))[i] = Real(0);
 }
 
 // ------------------------------------------------------------ pair passes
@@ -209,17 +254,18 @@ template <typename Rec>
 struct TileStage {
   static constexpr int kChunks = 64 * (int)sizeof(Rec) / 16;
   static constexpr int kPer = (kChunks + kThreads - 1) / kThreads;
-  uint4 r[kPer];
-  __device__ __forceinline__ void load(const Rec* __restrict__ src, int tile) {
-    const uint4* s = reinterpret_cast<const uint4*>(src + (int64_t)tile * kTile);
+  Chunk16 r[kPer];
+  template <typename P>
+  __device__ __forceinline__ void load(P src, int tile) {
+    const HK_GLOBAL Chunk16* s = (const HK_GLOBAL Chunk16*)(src + (int64_t)tile * kTile);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int c = threadIdx.x + k * kThreads;
-      if (c < kChunks) r[k] = s[c];
+      if (c < kChunks) { r[k].a = s[c].a; r[k].b = s[c].b; r[k].c = s[c].c; r[k].d = s[c].d; }
     }
   }
   __device__ __forceinline__ void store(Rec* dst) {
-    uint4* s = reinterpret_cast<uint4*>(dst);
+    Chunk16* s = reinterpret_cast<Chunk16*>(dst);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int c = threadIdx.x + k * kThreads;
@@ -300,21 +346,23 @@ __device__ __forceinline__ void pass1_tile(Pass1Rows<D, MIX>& S, const typename 
 }
 
 template <int D, bool MIX>
-__global__ void __launch_bounds__(kThreads) k_pass1(const typename Traits<D, MIX>::Rec* __restrict__ rec,
-                                                     const int* __restrict__ first, const int2* __restrict__ items,
-                                                     const int* __restrict__ status, double* __restrict__ prow,
-                                                     typename Traits<D, MIX>::ColT* __restrict__ pcol, KParams kp) {
-  using Tr = Traits<D, MIX>;
-  using Real = typename Tr::Real;
-  using ColT = typename Tr::ColT;
-  using Rec = typename Tr::Rec;
+__global__ void __launch_bounds__(kThreads) k_pass1(const ReqDesc* __restrict__ reqs, int nreq) {
+  using Rec = typename Traits<D, false>::Rec;
+  using Real = double;
+  using ColT = double;
   constexpr int R = kRowsPerLane;
   constexpr int NQ = 3;
   __shared__ Rec s_rec[2][kTile];
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
-  if (status[kStData] != 0) return;
-  const int2 it = items[blockIdx.x];
-  const int band = it.x, chunk = it.y;
+  const int rid = find_req(reqs, nreq, blockIdx.x, 0);
+  const ReqDesc& rq = reqs[rid];
+  if (uni(glb(rq.status)[kStData]) != 0) return;
+  const KParams& kp = rq.kp;
+  const auto rec = glb(static_cast<const Rec*>(rq.rec));
+  const auto first = glb(rq.first);
+  const auto pcol = glb(static_cast<ColT*>(rq.pcol));
+  const int item = blockIdx.x - rq.blk_items;
+  const int band = uni(glb(rq.items)[item].x), chunk = uni(glb(rq.items)[item].y);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row_base = band * kBandRows;
   const int row_end = min(kp.n, row_base + kBandRows);
@@ -322,34 +370,36 @@ __global__ void __launch_bounds__(kThreads) k_pass1(const typename Traits<D, MIX
   const int tile0 = chunk * kp.L;
   const int tile1 = min(tile0 + kp.L, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
-  const int first_min = first[row_base];
+  const int first_min = uni(first[row_base]);
 
-  Pass1Rows<D, MIX> S;
+  Pass1Rows<D, false> S;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int gi = row_base + wave * 64 * R + r * 64 + lane;
-    const Rec rr = rec[gi];
+    Rec rr;
+#pragma unroll
+    for (int q = 0; q < (int)(sizeof(Rec) / sizeof(rr.v[0])); ++q) rr.v[q] = rec[gi].v[q];
 #pragma unroll
     for (int q = 0; q < D; ++q) S.x[r][q] = rr.v[q];
     S.t[r] = rr.v[D];
     S.first[r] = first[gi];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) { S.a[r][q] = 0; S.acc[r][q] = 0.0; }
+    for (int q = 0; q < 6; ++q) { S.a[r][q] = Real(0); S.acc[r][q] = 0.0; }
   }
   {
     ColT* z = &s_acc[0][0][0][0];
-    for (int i = threadIdx.x; i < 2 * kWaves * NQ * kTile; i += kThreads) z[i] = ColT(0);
+    for (int e = threadIdx.x; e < 2 * kWaves * NQ * kTile; e += kThreads) z[e] = ColT(0);
   }
   TileStage<Rec> stage;
   stage.load(rec, tile0);
   for (int tile = tile0; tile < tile1; ++tile) {
     const int buf = (tile - tile0) & 1;
-    stage.store(s_rec[buf]);
+    stage.store(&s_rec[buf][0]);
     __syncthreads();
     if (tile + 1 < tile1) stage.load(rec, tile + 1);
-    if (tile > tile0 && threadIdx.x < NQ * kTile) {
+    for (int e = threadIdx.x; tile > tile0 && e < NQ * kTile; e += kThreads) {
       // column sums of the previous tile: fixed-order sum over the waves
-      const int q = threadIdx.x >> 6, c = threadIdx.x & 63;
+      const int q = e >> 6, c = e & 63;
       ColT s = ColT(0);
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) { s += s_acc[buf ^ 1][w][q][c]; s_acc[buf ^ 1][w][q][c] = ColT(0); }
@@ -358,17 +408,12 @@ __global__ void __launch_bounds__(kThreads) k_pass1(const typename Traits<D, MIX
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
     if (full) pass1_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
     else pass1_tile<D, MIX, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
-    if (MIX) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int q = 0; q < 6; ++q) { S.acc[r][q] += (double)S.a[r][q]; S.a[r][q] = 0; }
-    }
+
   }
   __syncthreads();
-  if (threadIdx.x < NQ * kTile) {
+  for (int e = threadIdx.x; e < NQ * kTile; e += kThreads) {
     const int buf = (tile1 - 1 - tile0) & 1;
-    const int q = threadIdx.x >> 6, c = threadIdx.x & 63;
+    const int q = e >> 6, c = e & 63;
     ColT s = ColT(0);
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s += s_acc[buf][w][q][c];
@@ -378,8 +423,7 @@ __global__ void __launch_bounds__(kThreads) k_pass1(const typename Traits<D, MIX
   for (int r = 0; r < R; ++r) {
     const int lr = wave * 64 * R + r * 64 + lane;
 #pragma unroll
-    for (int q = 0; q < 6; ++q)
-      prow[((int64_t)blockIdx.x * 6 + q) * kBandRows + lr] = MIX ? S.acc[r][q] : (double)S.a[r][q];
+    for (int q = 0; q < 6; ++q) glb(rq.prow)[((int64_t)item * 6 + q) * kBandRows + lr] = S.a[r][q];
   }
 }
 
@@ -450,23 +494,23 @@ __device__ __forceinline__ void pass2_tile(Pass2Rows<D, MIX>& S, const typename 
 }
 
 template <int D, bool MIX>
-__global__ void __launch_bounds__(kThreads) k_pass2(const typename Traits<D, MIX>::Rec* __restrict__ rec,
-                                                     const int* __restrict__ first, const int2* __restrict__ items,
-                                                     const int* __restrict__ status,
-                                                     const typename Traits<D, MIX>::Real* __restrict__ psrow,
-                                                     double* __restrict__ prow,
-                                                     typename Traits<D, MIX>::ColT* __restrict__ pcol, KParams kp) {
-  using Tr = Traits<D, MIX>;
-  using Real = typename Tr::Real;
-  using ColT = typename Tr::ColT;
-  using Rec = typename Tr::Rec;
+__global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ reqs, int nreq) {
+  using Rec = typename Traits<D, false>::Rec;
+  using Real = double;
+  using ColT = double;
   constexpr int R = kRowsPerLane;
   constexpr int NQ = D;
   __shared__ Rec s_rec[2][kTile];
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
-  if (status[kStData] != 0 || status[kStZero] != 0) return;
-  const int2 it = items[blockIdx.x];
-  const int band = it.x, chunk = it.y;
+  const int rid = find_req(reqs, nreq, blockIdx.x, 0);
+  const ReqDesc& rq = reqs[rid];
+  if (uni(glb(rq.status)[kStData]) != 0 || uni(glb(rq.status)[kStZero]) != 0) return;
+  const KParams& kp = rq.kp;
+  const auto rec = glb(static_cast<const Rec*>(rq.rec));
+  const auto first = glb(rq.first);
+  const auto pcol = glb(static_cast<ColT*>(rq.pcol));
+  const int item = blockIdx.x - rq.blk_items;
+  const int band = uni(glb(rq.items)[item].x), chunk = uni(glb(rq.items)[item].y);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row_base = band * kBandRows;
   const int row_end = min(kp.n, row_base + kBandRows);
@@ -474,32 +518,35 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const typename Traits<D, MIX
   const int tile0 = chunk * kp.L;
   const int tile1 = min(tile0 + kp.L, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
-  const int first_min = first[row_base];
+  const int first_min = uni(first[row_base]);
 
-  Pass2Rows<D, MIX> S;
+  Pass2Rows<D, false> S;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int gi = row_base + wave * 64 * R + r * 64 + lane;
-    const Rec rr = rec[gi];
+    Rec rr;
 #pragma unroll
-    for (int q = 0; q < D; ++q) { S.x[r][q] = rr.v[q]; S.g[r][q] = 0; S.acc[r][q] = 0.0; }
+    for (int q = 0; q < (int)(sizeof(Rec) / sizeof(rr.v[0])); ++q) rr.v[q] = rec[gi].v[q];
+#pragma unroll
+    for (int q = 0; q < D; ++q) { S.x[r][q] = rr.v[q]; S.g[r][q] = Real(0);  }
     S.t[r] = rr.v[D];
     S.pb[r] = rr.v[D + 1];
-    S.ps[r] = psrow[gi];
+    S.ps[r] = glb(static_cast<const Real*>(rq.ps))[gi];
     S.first[r] = first[gi];
   }
   {
     ColT* z = &s_acc[0][0][0][0];
-    for (int i = threadIdx.x; i < 2 * kWaves * NQ * kTile; i += kThreads) z[i] = ColT(0);
+    for (int e = threadIdx.x; e < 2 * kWaves * NQ * kTile; e += kThreads) z[e] = ColT(0);
   }
   TileStage<Rec> stage;
   stage.load(rec, tile0);
   for (int tile = tile0; tile < tile1; ++tile) {
     const int buf = (tile - tile0) & 1;
-    stage.store(s_rec[buf]);
+    stage.store(&s_rec[buf][0]);
     __syncthreads();
     if (tile + 1 < tile1) stage.load(rec, tile + 1);
     for (int e = threadIdx.x; tile > tile0 && e < NQ * kTile; e += kThreads) {
+      // column sums of the previous tile: fixed-order sum over the waves
       const int q = e >> 6, c = e & 63;
       ColT s = ColT(0);
 #pragma unroll
@@ -509,12 +556,7 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const typename Traits<D, MIX
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
     if (full) pass2_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
     else pass2_tile<D, MIX, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
-    if (MIX) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int q = 0; q < D; ++q) { S.acc[r][q] += (double)S.g[r][q]; S.g[r][q] = 0; }
-    }
+
   }
   __syncthreads();
   for (int e = threadIdx.x; e < NQ * kTile; e += kThreads) {
@@ -529,8 +571,7 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const typename Traits<D, MIX
   for (int r = 0; r < R; ++r) {
     const int lr = wave * 64 * R + r * 64 + lane;
 #pragma unroll
-    for (int q = 0; q < D; ++q)
-      prow[((int64_t)blockIdx.x * D + q) * kBandRows + lr] = MIX ? S.acc[r][q] : (double)S.g[r][q];
+    for (int q = 0; q < D; ++q) glb(rq.prow)[((int64_t)item * D + q) * kBandRows + lr] = S.g[r][q];
   }
 }
 
@@ -600,18 +641,23 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
 }
 
 template <int D>
-__global__ void __launch_bounds__(kThreads) k_pass1_mixed(const typename Traits<D, true>::Rec* __restrict__ rec,
-                                                           const int* __restrict__ first, const int2* __restrict__ items,
-                                                           const int* __restrict__ status, double* __restrict__ prow,
-                                                           float* __restrict__ pcol, KParams kp) {
+__global__ void __launch_bounds__(kThreads) k_pass1_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
   using Rec = typename Traits<D, true>::Rec;
+  using Real = float;
+  using ColT = float;
   constexpr int R = kRowsPerLane;
   constexpr int NQ = 3;
   __shared__ Rec s_rec[2][2 * kTile];
-  __shared__ float s_acc[2][kWaves][NQ][kTile];
-  if (status[kStData] != 0) return;
-  const int2 it = items[blockIdx.x];
-  const int band = it.x, chunk = it.y;
+  __shared__ ColT s_acc[2][kWaves][NQ][kTile];
+  const int rid = find_req(reqs, nreq, blockIdx.x, 0);
+  const ReqDesc& rq = reqs[rid];
+  if (uni(glb(rq.status)[kStData]) != 0) return;
+  const KParams& kp = rq.kp;
+  const auto rec = glb(static_cast<const Rec*>(rq.rec));
+  const auto first = glb(rq.first);
+  const auto pcol = glb(static_cast<ColT*>(rq.pcol));
+  const int item = blockIdx.x - rq.blk_items;
+  const int band = uni(glb(rq.items)[item].x), chunk = uni(glb(rq.items)[item].y);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row_base = band * kBandRows;
   const int row_end = min(kp.n, row_base + kBandRows);
@@ -619,19 +665,21 @@ __global__ void __launch_bounds__(kThreads) k_pass1_mixed(const typename Traits<
   const int tile0 = chunk * kp.L;
   const int tile1 = min(tile0 + kp.L, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
-  const int first_min = first[row_base];
+  const int first_min = uni(first[row_base]);
 
   Pass1Rows<D, true> S;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int gi = row_base + wave * 64 * R + r * 64 + lane;
-    const Rec rr = rec[gi];
+    Rec rr;
+#pragma unroll
+    for (int q = 0; q < (int)(sizeof(Rec) / sizeof(rr.v[0])); ++q) rr.v[q] = rec[gi].v[q];
 #pragma unroll
     for (int q = 0; q < D; ++q) S.x[r][q] = rr.v[q];
     S.t[r] = rr.v[D];
     S.first[r] = first[gi];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) { S.a[r][q] = 0.f; S.acc[r][q] = 0.0; }
+    for (int q = 0; q < 6; ++q) { S.a[r][q] = Real(0); S.acc[r][q] = 0.0; }
   }
   TileStage<Rec> stage;
   stage.load(rec, tile0);
@@ -641,11 +689,12 @@ __global__ void __launch_bounds__(kThreads) k_pass1_mixed(const typename Traits<
     stage.store(&s_rec[buf][kTile]);
     __syncthreads();
     if (tile + 1 < tile1) stage.load(rec, tile + 1);
-    if (tile > tile0 && threadIdx.x < NQ * kTile) {
-      const int q = threadIdx.x >> 6, c = threadIdx.x & 63;
-      float s = 0.f;
+    for (int e = threadIdx.x; tile > tile0 && e < NQ * kTile; e += kThreads) {
+      // column sums of the previous tile: fixed-order sum over the waves
+      const int q = e >> 6, c = e & 63;
+      ColT s = ColT(0);
 #pragma unroll
-      for (int w = 0; w < kWaves; ++w) s += s_acc[buf ^ 1][w][q][c];
+      for (int w = 0; w < kWaves; ++w) { s += s_acc[buf ^ 1][w][q][c]; }
       pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
     }
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
@@ -657,10 +706,10 @@ __global__ void __launch_bounds__(kThreads) k_pass1_mixed(const typename Traits<
       for (int q = 0; q < 6; ++q) { S.acc[r][q] += (double)S.a[r][q]; S.a[r][q] = 0.f; }
   }
   __syncthreads();
-  if (threadIdx.x < NQ * kTile) {
+  for (int e = threadIdx.x; e < NQ * kTile; e += kThreads) {
     const int buf = (tile1 - 1 - tile0) & 1;
-    const int q = threadIdx.x >> 6, c = threadIdx.x & 63;
-    float s = 0.f;
+    const int q = e >> 6, c = e & 63;
+    ColT s = ColT(0);
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s += s_acc[buf][w][q][c];
     pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile1 - 1) * kTile + c] = s;
@@ -669,7 +718,7 @@ __global__ void __launch_bounds__(kThreads) k_pass1_mixed(const typename Traits<
   for (int r = 0; r < R; ++r) {
     const int lr = wave * 64 * R + r * 64 + lane;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) prow[((int64_t)blockIdx.x * 6 + q) * kBandRows + lr] = S.acc[r][q];
+    for (int q = 0; q < 6; ++q) glb(rq.prow)[((int64_t)item * 6 + q) * kBandRows + lr] = S.acc[r][q];
   }
 }
 
@@ -724,19 +773,23 @@ __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const ty
 }
 
 template <int D>
-__global__ void __launch_bounds__(kThreads) k_pass2_mixed(const typename Traits<D, true>::Rec* __restrict__ rec,
-                                                           const int* __restrict__ first, const int2* __restrict__ items,
-                                                           const int* __restrict__ status, const float* __restrict__ psrow,
-                                                           double* __restrict__ prow, float* __restrict__ pcol,
-                                                           KParams kp) {
+__global__ void __launch_bounds__(kThreads) k_pass2_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
   using Rec = typename Traits<D, true>::Rec;
+  using Real = float;
+  using ColT = float;
   constexpr int R = kRowsPerLane;
   constexpr int NQ = D;
   __shared__ Rec s_rec[2][2 * kTile];
-  __shared__ float s_acc[2][kWaves][NQ][kTile];
-  if (status[kStData] != 0 || status[kStZero] != 0) return;
-  const int2 it = items[blockIdx.x];
-  const int band = it.x, chunk = it.y;
+  __shared__ ColT s_acc[2][kWaves][NQ][kTile];
+  const int rid = find_req(reqs, nreq, blockIdx.x, 0);
+  const ReqDesc& rq = reqs[rid];
+  if (uni(glb(rq.status)[kStData]) != 0 || uni(glb(rq.status)[kStZero]) != 0) return;
+  const KParams& kp = rq.kp;
+  const auto rec = glb(static_cast<const Rec*>(rq.rec));
+  const auto first = glb(rq.first);
+  const auto pcol = glb(static_cast<ColT*>(rq.pcol));
+  const int item = blockIdx.x - rq.blk_items;
+  const int band = uni(glb(rq.items)[item].x), chunk = uni(glb(rq.items)[item].y);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row_base = band * kBandRows;
   const int row_end = min(kp.n, row_base + kBandRows);
@@ -744,18 +797,20 @@ __global__ void __launch_bounds__(kThreads) k_pass2_mixed(const typename Traits<
   const int tile0 = chunk * kp.L;
   const int tile1 = min(tile0 + kp.L, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
-  const int first_min = first[row_base];
+  const int first_min = uni(first[row_base]);
 
   Pass2Rows<D, true> S;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int gi = row_base + wave * 64 * R + r * 64 + lane;
-    const Rec rr = rec[gi];
+    Rec rr;
 #pragma unroll
-    for (int q = 0; q < D; ++q) { S.x[r][q] = rr.v[q]; S.g[r][q] = 0.f; S.acc[r][q] = 0.0; }
+    for (int q = 0; q < (int)(sizeof(Rec) / sizeof(rr.v[0])); ++q) rr.v[q] = rec[gi].v[q];
+#pragma unroll
+    for (int q = 0; q < D; ++q) { S.x[r][q] = rr.v[q]; S.g[r][q] = Real(0); S.acc[r][q] = 0.0; }
     S.t[r] = rr.v[D];
     S.pb[r] = rr.v[D + 1];
-    S.ps[r] = psrow[gi];
+    S.ps[r] = glb(static_cast<const Real*>(rq.ps))[gi];
     S.first[r] = first[gi];
   }
   TileStage<Rec> stage;
@@ -767,10 +822,11 @@ __global__ void __launch_bounds__(kThreads) k_pass2_mixed(const typename Traits<
     __syncthreads();
     if (tile + 1 < tile1) stage.load(rec, tile + 1);
     for (int e = threadIdx.x; tile > tile0 && e < NQ * kTile; e += kThreads) {
+      // column sums of the previous tile: fixed-order sum over the waves
       const int q = e >> 6, c = e & 63;
-      float s = 0.f;
+      ColT s = ColT(0);
 #pragma unroll
-      for (int w = 0; w < kWaves; ++w) s += s_acc[buf ^ 1][w][q][c];
+      for (int w = 0; w < kWaves; ++w) { s += s_acc[buf ^ 1][w][q][c]; }
       pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
     }
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
@@ -785,7 +841,7 @@ __global__ void __launch_bounds__(kThreads) k_pass2_mixed(const typename Traits<
   for (int e = threadIdx.x; e < NQ * kTile; e += kThreads) {
     const int buf = (tile1 - 1 - tile0) & 1;
     const int q = e >> 6, c = e & 63;
-    float s = 0.f;
+    ColT s = ColT(0);
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) s += s_acc[buf][w][q][c];
     pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile1 - 1) * kTile + c] = s;
@@ -794,7 +850,7 @@ __global__ void __launch_bounds__(kThreads) k_pass2_mixed(const typename Traits<
   for (int r = 0; r < R; ++r) {
     const int lr = wave * 64 * R + r * 64 + lane;
 #pragma unroll
-    for (int q = 0; q < D; ++q) prow[((int64_t)blockIdx.x * D + q) * kBandRows + lr] = S.acc[r][q];
+    for (int q = 0; q < D; ++q) glb(rq.prow)[((int64_t)item * D + q) * kBandRows + lr] = S.acc[r][q];
   }
 }
 
@@ -802,51 +858,76 @@ __global__ void __launch_bounds__(kThreads) k_pass2_mixed(const typename Traits<
 
 // Per event: fixed-order sum of the row partials (this band's items) and the
 // column partials (bands from this one to the last), conversion to the raw
-// sums K, R, U, J, V, W (times exp(sigma)), and the recompute flag.
-template <bool MIX, typename ColT>
-__global__ void __launch_bounds__(256) k_reduce1(const double* __restrict__ prow, const ColT* __restrict__ pcol,
-                                                  const int2* __restrict__ band_info, const int* __restrict__ status,
-                                                  double* __restrict__ sums, double* __restrict__ sigma,
-                                                  int* __restrict__ flags, KParams kp) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kp.n || status[kStData] != 0) return;
-  const int b = i / kBandRows, lr = i % kBandRows;
-  const int2 bi = band_info[b];
-  double s[6] = {0, 0, 0, 0, 0, 0};
-  for (int c = 0; c < bi.y; ++c) {
-    const double* p = prow + (int64_t)(bi.x + c) * 6 * kBandRows + lr;
+// sums K, R, U, J, V, W (times exp(sigma)), and the recompute flag.  Flagged
+// rows of each block are staged in index order for k_flaglist.
+template <bool MIX>
+__global__ void __launch_bounds__(kEvBlock) k_reduce1(const ReqDesc* __restrict__ reqs, int nreq) {
+  using ColT = typename std::conditional<MIX, float, double>::type;
+  __shared__ int s_cnt[kEvBlock / 64];
+  const int rid = find_req(reqs, nreq, blockIdx.x, 1);
+  const ReqDesc& rq = reqs[rid];
+  if (glb(rq.status)[kStData] != 0) return;
+  const KParams& kp = rq.kp;
+  const int lb = blockIdx.x - rq.blk_ev;
+  const int i = lb * kEvBlock + threadIdx.x;
+  bool flag = false;
+  if (i < kp.n) {
+    const int b = i / kBandRows, lr = i % kBandRows;
+    const IPair bi{glb(rq.band)[b].x, glb(rq.band)[b].y};
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int c = 0; c < bi.y; ++c) {
+      const auto p = glb(rq.prow) + (int64_t)(bi.x + c) * 6 * kBandRows + lr;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) s[q] += p[(int64_t)q * kBandRows];
-  }
-  for (int I = b; I < kp.nb; ++I) {
-    const ColT* p = pcol + (int64_t)I * 3 * kp.n_pad + i;
+      for (int q = 0; q < 6; ++q) s[q] += p[(int64_t)q * kBandRows];
+    }
+    const auto pcol = glb(static_cast<const ColT*>(rq.pcol));
+    for (int I = b; I < kp.nb; ++I) {
+      const auto p = pcol + (int64_t)I * 3 * kp.n_pad + i;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) s[q] += (double)p[(int64_t)q * kp.n_pad];
-  }
-  if (MIX) {
-    s[1] /= (double)kp.Ab;
-    s[2] /= (double)kp.Bt;
-    s[4] /= (double)kp.Gs;
-    s[5] /= (double)kp.Ws;
-  }
-  const double lam = kp.cbg * s[0] + kp.cse * s[3];
-  const bool flag = !(lam >= kp.cmax * exp2(kp.flag_floor));
+      for (int q = 0; q < 3; ++q) s[q] += (double)p[(int64_t)q * kp.n_pad];
+    }
+    if (MIX) {
+      s[1] /= (double)kp.Ab;
+      s[2] /= (double)kp.Bt;
+      s[4] /= (double)kp.Gs;
+      s[5] /= (double)kp.Ws;
+    }
+    const double lam = kp.cbg * s[0] + kp.cse * s[3];
+    flag = !(lam >= kp.cmax * exp2(kp.flag_floor));
 #pragma unroll
-  for (int q = 0; q < 6; ++q) sums[(int64_t)i * 6 + q] = s[q];
-  sigma[i] = kp.sigma_main;
-  flags[i] = flag ? 1 : 0;
+    for (int q = 0; q < 6; ++q) glb(rq.sums)[(int64_t)i * 6 + q] = s[q];
+    glb(rq.sigma)[i] = kp.sigma_main;
+    glb(rq.flags)[i] = flag ? 1 : 0;
+  }
+  // stage this block's flagged rows in index order (wave ballots, then waves in order)
+  const unsigned long long m = __ballot(flag);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) s_cnt[w] = __popcll(m);
+  __syncthreads();
+  int before = 0;
+  for (int ww = 0; ww < w; ++ww) before += s_cnt[ww];
+  if (flag) {
+    const int pos = before + __popcll(m & ((1ull << lane) - 1ull));
+    glb(rq.bstage)[(int64_t)lb * kEvBlock + pos] = i;
+  }
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int ww = 0; ww < kEvBlock / 64; ++ww) tot += s_cnt[ww];
+    glb(rq.bcount)[lb] = tot;
+  }
 }
 
-// Ordered list of the flagged rows (one workgroup of 1024 threads).
-__global__ void __launch_bounds__(1024) k_flaglist(const int* __restrict__ flags, int n, int* __restrict__ status,
-                                                    int* __restrict__ list) {
+// Ordered list of the flagged rows of each request (one workgroup of 1024
+// threads per request): scan of the per-block counts, then copy the staged rows.
+__global__ void __launch_bounds__(1024) k_flaglist(const ReqDesc* __restrict__ reqs) {
   __shared__ int s_scan[1024];
-  const int tid = threadIdx.x;
-  if (status[kStData] != 0) return;
-  const int per = (n + 1023) / 1024;
-  const int lo = min(n, tid * per), hi = min(n, lo + per);
+  const ReqDesc& rq = reqs[blockIdx.x];
+  if (glb(rq.status)[kStData] != 0) return;
+  const int nblk = rq.kp.nblk, tid = threadIdx.x;
+  const int per = (nblk + 1023) / 1024;
+  const int lo = min(nblk, tid * per), hi = min(nblk, lo + per);
   int cnt = 0;
-  for (int i = lo; i < hi; ++i) cnt += flags[i];
+  for (int b = lo; b < hi; ++b) cnt += glb(rq.bcount)[b];
   s_scan[tid] = cnt;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -856,29 +937,43 @@ __global__ void __launch_bounds__(1024) k_flaglist(const int* __restrict__ flags
     __syncthreads();
   }
   int pos = s_scan[tid] - cnt;
-  for (int i = lo; i < hi; ++i)
-    if (flags[i]) list[pos++] = i;
-  if (tid == 1023) status[kStFlagCount] = s_scan[1023];
+  for (int b = lo; b < hi; ++b) {
+    const int c = glb(rq.bcount)[b];
+    for (int k = 0; k < c; ++k) {
+      const int i = glb(rq.bstage)[(int64_t)b * kEvBlock + k];
+      glb(rq.list)[pos] = i;
+      glb(rq.listpos)[i] = pos;
+      ++pos;
+    }
+  }
+  if (tid == 1023) glb(rq.status)[kStFlagCount] = s_scan[1023];
 }
 
-// Exact float64 recomputation of the six row sums of each flagged row, with a
-// per-row log scale sigma = max_j log(weighted pair term): two sweeps over all
-// partners, so no term that matters can underflow.
+// Exact float64 recomputation of the six row sums of each flagged row.  The
+// partners are split into kFixSeg segments; each (row, segment) task finds the
+// segment's largest log pair term m_s, then sums exp(term - m_s) -- no term that
+// matters can underflow.  k_final1 merges the segments in a fixed order.
+// fixpart[(f * kFixSeg + s) * 8 + q]: q < 6 the unweighted sums times exp(-m_s), q = 6 m_s.
 template <int D>
-__global__ void __launch_bounds__(256) k_fix1(const double* __restrict__ x, const double* __restrict__ t,
-                                               const int* __restrict__ status, const int* __restrict__ list,
-                                               double* __restrict__ sums, double* __restrict__ sigma, KParams kp) {
+__global__ void __launch_bounds__(256) k_fix1(const ReqDesc* __restrict__ reqs) {
   __shared__ double sh[256];
-  if (status[kStData] != 0) return;
-  const int cnt = status[kStFlagCount];
-  for (int f = blockIdx.x; f < cnt; f += gridDim.x) {
-    const int i = list[f];
+  const ReqDesc& rq = reqs[blockIdx.y];
+  if (glb(rq.status)[kStData] != 0) return;
+  const KParams& kp = rq.kp;
+  const auto x = glb(rq.x);
+  const auto t = glb(rq.t);
+  const int cnt = glb(rq.status)[kStFlagCount];
+  const int seg = (kp.n + kFixSeg - 1) / kFixSeg;
+  for (int task = blockIdx.x; task < cnt * kFixSeg; task += gridDim.x) {
+    const int f = task / kFixSeg, sg = task % kFixSeg;
+    const int i = glb(rq.list)[f];
+    const int j0 = sg * seg, j1 = min(kp.n, j0 + seg);
     double xi[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) xi[q] = x[(int64_t)i * D + q];
     const double ti = t[i];
     double m = -INFINITY;
-    for (int j = threadIdx.x; j < kp.n; j += 256) {
+    for (int j = j0 + threadIdx.x; j < j1; j += 256) {
       if (j == i) continue;
       double r2 = 0;
 #pragma unroll
@@ -888,29 +983,29 @@ __global__ void __launch_bounds__(256) k_fix1(const double* __restrict__ x, cons
       if (dt > 0.0) m = fmax(m, kp.log_cse - kp.omega * dt - kp.gamma * r2);
     }
     m = block_max_256(m, sh);
-    if (!(m > -INFINITY)) m = 0.0;   // no active partner: lambda is exactly 0
+    const double msub = m > -INFINITY ? m : 0.0;
     double a[6] = {0, 0, 0, 0, 0, 0};
-    for (int j = threadIdx.x; j < kp.n; j += 256) {
+    for (int j = j0 + threadIdx.x; j < j1; j += 256) {
       if (j == i) continue;
       double r2 = 0;
 #pragma unroll
       for (int q = 0; q < D; ++q) { const double dx = xi[q] - x[(int64_t)j * D + q]; r2 += dx * dx; }
       const double dt = ti - t[j];
       if (dt != 0.0) {
-        const double e = exp(-kp.alpha * r2 - kp.beta * dt * dt - m);
+        const double e = exp(-kp.alpha * r2 - kp.beta * dt * dt - msub);
         a[0] += e; a[1] += e * r2; a[2] += e * dt * dt;
       }
       if (dt > 0.0) {
-        const double e = exp(-kp.omega * dt - kp.gamma * r2 - m);
+        const double e = exp(-kp.omega * dt - kp.gamma * r2 - msub);
         a[3] += e; a[4] += e * r2; a[5] += e * dt;
       }
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       const double v = block_sum_256(a[q], sh);
-      if (threadIdx.x == 0) sums[(int64_t)i * 6 + q] = v;
+      if (threadIdx.x == 0) glb(rq.fixpart)[((int64_t)f * kFixSeg + sg) * 8 + q] = v;
     }
-    if (threadIdx.x == 0) sigma[i] = m;
+    if (threadIdx.x == 0) glb(rq.fixpart)[((int64_t)f * kFixSeg + sg) * 8 + 6] = m;
   }
 }
 
@@ -920,23 +1015,47 @@ __device__ __forceinline__ double std_normal_pdf(double z) { return 0.3989422804
 // Per event: lambda, log lambda, compensator, log-likelihood term and the six
 // parameter-gradient terms; per-block fixed-order partials; the pass-2 factors.
 template <int D, bool MIX>
-__global__ void __launch_bounds__(256) k_final1(const double* __restrict__ t, const int* __restrict__ status,
-                                                 const double* __restrict__ dconst, const double* __restrict__ sums,
-                                                 const double* __restrict__ sigma, const int* __restrict__ flags,
-                                                 typename Traits<D, MIX>::Rec* __restrict__ rec,
-                                                 typename Traits<D, MIX>::Real* __restrict__ psrow,
-                                                 double* __restrict__ logl, double* __restrict__ blockpart, KParams kp) {
+__global__ void __launch_bounds__(kEvBlock) k_final1(const ReqDesc* __restrict__ reqs, int nreq) {
   using Real = typename Traits<D, MIX>::Real;
-  __shared__ double sh[256];
-  if (status[kStData] != 0) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  using Rec = typename Traits<D, MIX>::Rec;
+  __shared__ double sh[kEvBlock];
+  const int rid = find_req(reqs, nreq, blockIdx.x, 1);
+  const ReqDesc& rq = reqs[rid];
+  if (glb(rq.status)[kStData] != 0) return;
+  const KParams& kp = rq.kp;
+  const int lb = blockIdx.x - rq.blk_ev;
+  const int i = lb * kEvBlock + threadIdx.x;
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (i < kp.n) {
-    const double* s = sums + (int64_t)i * 6;
-    const double sg = sigma[i];
+    double s[6];
+    double sg;
+    const bool fl = glb(rq.flags)[i] != 0;
+    if (fl) {
+      // merge the fix-up segments: common scale m = max_s m_s
+      const auto fp = glb(rq.fixpart) + (int64_t)glb(rq.listpos)[i] * kFixSeg * 8;
+      double m = -INFINITY;
+      for (int g = 0; g < kFixSeg; ++g) m = fmax(m, fp[g * 8 + 6]);
+      for (int q = 0; q < 6; ++q) s[q] = 0.0;
+      if (m > -INFINITY) {
+        for (int g = 0; g < kFixSeg; ++g) {
+          const double mg = fp[g * 8 + 6];
+          if (mg > -INFINITY) {
+            const double w = exp(mg - m);
+            for (int q = 0; q < 6; ++q) s[q] += fp[g * 8 + q] * w;
+          }
+        }
+        sg = m;
+      } else {
+        sg = 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) s[q] = glb(rq.sums)[(int64_t)i * 6 + q];
+      sg = glb(rq.sigma)[i];
+    }
     const double lt = kp.cbg * s[0] + kp.cse * s[3];   // lambda * exp(-sigma)
     const double L = log(lt) + sg;
-    const double T = dconst[0], ti = t[i];
+    const double T = glb(rq.dconst)[0], ti = rq.t[i];
     const double a = (T - ti) / kp.tau_t, b = -ti / kp.tau_t;
     const double cdf_diff = std_normal_cdf(a) - std_normal_cdf(b);
     const double decay = exp(-kp.omega * (T - ti));
@@ -952,40 +1071,41 @@ __global__ void __launch_bounds__(256) k_final1(const double* __restrict__ t, co
     v[5] = kp.cse * (s[3] / kp.omega - s[5]) * il - kp.theta * (T - ti) * decay;
     v[6] = kp.cse * (s[4] / (kp.h * kp.h * kp.h) - D * s[3] / kp.h) * il;
     v[7] = lt > 0.0 ? 0.0 : 1.0;
-    logl[i] = L;
+    glb(rq.logl)[i] = L;
     // pass-2 factors: 1/lambda scaled to the main pass's 2^S terms
-    const bool fl = flags[i] != 0;
     const double pb = fl ? 0.0 : kp.cbg * kp.itx2 * il;
     const double ps = fl ? 0.0 : kp.cse * kp.ih2 * il;
-    rec[i].v[D + 1] = (Real)pb;
-    psrow[i] = (Real)ps;
+    glb(static_cast<Rec*>(rq.rec))[i].v[D + 1] = (Real)pb;
+    glb(static_cast<Real*>(rq.ps))[i] = (Real)ps;
   }
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const double r = block_sum_256(v[q], sh);
-    if (threadIdx.x == 0) blockpart[(int64_t)blockIdx.x * 8 + q] = r;
+    if (threadIdx.x == 0) glb(rq.bpart)[(int64_t)lb * 8 + q] = r;
   }
 }
 
-// Sum the per-block partials in block order; out8 = [ell, 6 gradients, status].
-__global__ void __launch_bounds__(256) k_final2(const double* __restrict__ blockpart, int nblk,
-                                                 int* __restrict__ status, double* __restrict__ out8) {
+// Sum the per-block partials in block order (one workgroup per request);
+// out8 = [ell, 6 gradients, status].
+__global__ void __launch_bounds__(256) k_final2(const ReqDesc* __restrict__ reqs) {
   __shared__ double sh[256];
+  const ReqDesc& rq = reqs[blockIdx.x];
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const int bad = status[kStData];
+  const int bad = glb(rq.status)[kStData];
   if (bad == 0) {
-    for (int b = threadIdx.x; b < nblk; b += 256)
+    for (int b = threadIdx.x; b < rq.kp.nblk; b += 256)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] += blockpart[(int64_t)b * 8 + q];
+      for (int q = 0; q < 8; ++q) v[q] += glb(rq.bpart)[(int64_t)b * 8 + q];
   }
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = block_sum_256(v[q], sh);
   if (threadIdx.x == 0) {
+    const auto out8 = glb(rq.out8);
     if (bad != 0) {
       for (int q = 0; q < 7; ++q) out8[q] = NAN;
       out8[7] = (double)bad;
     } else if (v[7] > 0.0) {
-      status[kStZero] = 1;
+      glb(rq.status)[kStZero] = 1;
       out8[0] = -INFINITY;
       for (int q = 1; q < 7; ++q) out8[q] = NAN;
       out8[7] = -4.0;
@@ -1001,28 +1121,27 @@ __global__ void __launch_bounds__(256) k_final2(const double* __restrict__ block
 // formed as exp(log-term - log lambda_j) in float64.
 // Sweep B (one thread per event i): sum over flagged j of c (x_j - x_i).
 template <int D>
-__global__ void __launch_bounds__(256) k_fix2b(const double* __restrict__ x, const double* __restrict__ t,
-                                                const int* __restrict__ status, const int* __restrict__ list,
-                                                const double* __restrict__ logl, double* __restrict__ gfix,
-                                                KParams kp) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kp.n || status[kStData] != 0 || status[kStZero] != 0) return;
-  const int cnt = status[kStFlagCount];
-  double g[D];
+__global__ void __launch_bounds__(kEvBlock) k_fix2b(const ReqDesc* __restrict__ reqs, int nreq) {
+  const int rid = find_req(reqs, nreq, blockIdx.x, 1);
+  const ReqDesc& rq = reqs[rid];
+  const KParams& kp = rq.kp;
+  const int i = (blockIdx.x - rq.blk_ev) * kEvBlock + threadIdx.x;
+  if (i >= kp.n || glb(rq.status)[kStData] != 0 || glb(rq.status)[kStZero] != 0) return;
+  const auto x = glb(rq.x);
+  const auto t = glb(rq.t);
+  const int cnt = glb(rq.status)[kStFlagCount];
+  double g[D], xi[D];
 #pragma unroll
-  for (int q = 0; q < D; ++q) g[q] = 0.0;
-  double xi[D];
-#pragma unroll
-  for (int q = 0; q < D; ++q) xi[q] = x[(int64_t)i * D + q];
+  for (int q = 0; q < D; ++q) { g[q] = 0.0; xi[q] = x[(int64_t)i * D + q]; }
   const double ti = t[i];
   for (int f = 0; f < cnt; ++f) {
-    const int j = list[f];
+    const int j = glb(rq.list)[f];
     if (j == i) continue;
     double dx[D], r2 = 0;
 #pragma unroll
     for (int q = 0; q < D; ++q) { dx[q] = x[(int64_t)j * D + q] - xi[q]; r2 += dx[q] * dx[q]; }
     const double dt = t[j] - ti;   // > 0 when j is the later event
-    const double Lj = logl[j];
+    const double Lj = glb(rq.logl)[j];
     double c = 0.0;
     if (dt != 0.0) c += exp(kp.log_cbg - kp.alpha * r2 - kp.beta * dt * dt - Lj) * kp.itx2;
     if (dt > 0.0) c += exp(kp.log_cse - kp.omega * dt - kp.gamma * r2 - Lj) * kp.ih2;
@@ -1030,29 +1149,33 @@ __global__ void __launch_bounds__(256) k_fix2b(const double* __restrict__ x, con
     for (int q = 0; q < D; ++q) g[q] += c * dx[q];
   }
 #pragma unroll
-  for (int q = 0; q < D; ++q) gfix[(int64_t)i * D + q] = g[q];
+  for (int q = 0; q < D; ++q) glb(rq.gfix)[(int64_t)i * D + q] = g[q];
 }
 
-// Sweep A (one workgroup per flagged row j): sum over all i of c (x_i - x_j),
-// added to the row's fix-up gradient.
+// Sweep A (tasks = flagged row x partner segment): partial sums over the
+// segment's events i of c (x_i - x_j) for flagged row j, merged by k_reduce2.
 template <int D>
-__global__ void __launch_bounds__(256) k_fix2a(const double* __restrict__ x, const double* __restrict__ t,
-                                                const int* __restrict__ status, const int* __restrict__ list,
-                                                const double* __restrict__ logl, double* __restrict__ gfix,
-                                                KParams kp) {
+__global__ void __launch_bounds__(256) k_fix2a(const ReqDesc* __restrict__ reqs) {
   __shared__ double sh[256];
-  if (status[kStData] != 0 || status[kStZero] != 0) return;
-  const int cnt = status[kStFlagCount];
-  for (int f = blockIdx.x; f < cnt; f += gridDim.x) {
-    const int j = list[f];
+  const ReqDesc& rq = reqs[blockIdx.y];
+  if (uni(glb(rq.status)[kStData]) != 0 || uni(glb(rq.status)[kStZero]) != 0) return;
+  const KParams& kp = rq.kp;
+  const auto x = glb(rq.x);
+  const auto t = glb(rq.t);
+  const int cnt = glb(rq.status)[kStFlagCount];
+  const int seg = (kp.n + kFixSeg - 1) / kFixSeg;
+  for (int task = blockIdx.x; task < cnt * kFixSeg; task += gridDim.x) {
+    const int f = task / kFixSeg, sg = task % kFixSeg;
+    const int j = glb(rq.list)[f];
+    const int i0 = sg * seg, i1 = min(kp.n, i0 + seg);
     double xj[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) xj[q] = x[(int64_t)j * D + q];
-    const double tj = t[j], Lj = logl[j];
+    const double tj = t[j], Lj = glb(rq.logl)[j];
     double g[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) g[q] = 0.0;
-    for (int i = threadIdx.x; i < kp.n; i += 256) {
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
       if (i == j) continue;
       double dx[D], r2 = 0;
 #pragma unroll
@@ -1067,41 +1190,58 @@ __global__ void __launch_bounds__(256) k_fix2a(const double* __restrict__ x, con
 #pragma unroll
     for (int q = 0; q < D; ++q) {
       const double v = block_sum_256(g[q], sh);
-      if (threadIdx.x == 0) gfix[(int64_t)j * D + q] += v;
+      if (threadIdx.x == 0) glb(rq.fixpart)[((int64_t)f * kFixSeg + sg) * 8 + q] = v;
     }
   }
 }
 
 // grad_x = row partials + column partials + fix-up terms (fixed order).
-template <int D, typename ColT>
-__global__ void __launch_bounds__(256) k_reduce2(const double* __restrict__ prow, const ColT* __restrict__ pcol,
-                                                  const int2* __restrict__ band_info, const int* __restrict__ status,
-                                                  const double* __restrict__ gfix, double* __restrict__ grad_x,
-                                                  KParams kp) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kp.n || status[kStData] != 0) return;
-  if (status[kStZero] != 0) {
+template <int D, bool MIX>
+__global__ void __launch_bounds__(kEvBlock) k_reduce2(const ReqDesc* __restrict__ reqs, int nreq) {
+  using ColT = typename std::conditional<MIX, float, double>::type;
+  const int rid = find_req(reqs, nreq, blockIdx.x, 1);
+  const ReqDesc& rq = reqs[rid];
+  const KParams& kp = rq.kp;
+  const int i = (blockIdx.x - rq.blk_ev) * kEvBlock + threadIdx.x;
+  if (i >= kp.n || glb(rq.status)[kStData] != 0 || rq.grad_x == nullptr) return;
+  const auto grad_x = glb(rq.grad_x);
+  if (glb(rq.status)[kStZero] != 0) {
 #pragma unroll
     for (int q = 0; q < D; ++q) grad_x[(int64_t)i * D + q] = NAN;
     return;
   }
   const int b = i / kBandRows, lr = i % kBandRows;
-  const int2 bi = band_info[b];
+  const IPair bi{glb(rq.band)[b].x, glb(rq.band)[b].y};
   double s[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) s[q] = 0.0;
   for (int c = 0; c < bi.y; ++c) {
-    const double* p = prow + (int64_t)(bi.x + c) * D * kBandRows + lr;
+    const auto p = glb(rq.prow) + (int64_t)(bi.x + c) * D * kBandRows + lr;
 #pragma unroll
     for (int q = 0; q < D; ++q) s[q] += p[(int64_t)q * kBandRows];
   }
+  const auto pcol = glb(static_cast<const ColT*>(rq.pcol));
   for (int I = b; I < kp.nb; ++I) {
-    const ColT* p = pcol + (int64_t)I * D * kp.n_pad + i;
+    const auto p = pcol + (int64_t)I * D * kp.n_pad + i;
 #pragma unroll
     for (int q = 0; q < D; ++q) s[q] += (double)p[(int64_t)q * kp.n_pad];
   }
 #pragma unroll
-  for (int q = 0; q < D; ++q) grad_x[(int64_t)i * D + q] = s[q] + gfix[(int64_t)i * D + q];
+  for (int q = 0; q < D; ++q) s[q] += glb(rq.gfix)[(int64_t)i * D + q];
+  if (glb(rq.flags)[i] != 0) {
+    const auto fp = glb(rq.fixpart) + (int64_t)glb(rq.listpos)[i] * kFixSeg * 8;
+    for (int g = 0; g < kFixSeg; ++g)
+#pragma unroll
+      for (int q = 0; q < D; ++q) s[q] += fp[g * 8 + q];
+  }
+#pragma unroll
+  for (int q = 0; q < D; ++q) grad_x[(int64_t)i * D + q] = s[q];
+}
+
+// Writes one request descriptor into device memory (the single-call entry
+// points; batched launches copy their descriptor arrays instead).
+__global__ void k_setdesc(ReqDesc d, ReqDesc* __restrict__ dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = d;
 }
 
 }  // namespace hawkes
