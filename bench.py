@@ -86,6 +86,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests per precision in the serving run (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -163,6 +166,10 @@ def main():
     f2, e2 = pass_work(d, "pass2")
     path_work = pairs_u * (f1 + f2 + (e1 + e2) * FLOP_EQ_PER_EXP)
 
+    serve = None
+    if args.serve_requests > 0:
+        serve = serving(args.serve_requests, args.serve_rate)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_seconds)
@@ -178,8 +185,23 @@ def main():
            "stage_ms": {k: round(float(v), 4) for k, v in zip(STAGES, stage_ms)},
            "fp64": fp64,
            "speedup_mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
+           "serve": serve,
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
+
+
+def serving(n_requests: int, rate: float):
+    """64 HMC chains over 64 datasets with N log-uniform in [1e3, 1e5] (D = 2,
+    coarsened to a 100 m grid), open-loop Poisson arrivals; mixed, then FP64."""
+    from paper_2010_02994_amd import loadgen
+    from paper_2010_02994_amd.serve import Server
+    out = {"chains": 64, "n_range": [1000, 100000], "offered_rate_req_s": rate}
+    with Server(hbm_budget_bytes=24 << 30, max_slots=64, streams=3) as srv:
+        chains = loadgen.Chains(srv, count=64)
+        for prec in ("mixed", "fp64"):
+            out[prec] = loadgen.run(srv, chains, rate=rate, n_requests=n_requests, prec=prec, warmup=100)
+        out["batches_launched"] = srv.stats()["batches_launched"]
+    return out
 
 
 def cpu_baseline(w, seconds: float):

@@ -103,6 +103,78 @@ int hawkes_grad_timed(const double* x, const double* t, int64_t n, int d, const 
                       double* loglik /* host or NULL */, double* grad_x /* device */,
                       double* grad_params /* host or NULL */, float* stage_ms /* host, 12 */);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of evaluation requests from many HMC chains
+ * (one request = one log-likelihood + gradient at new latent locations).
+ *
+ * A server owns an HBM arena of hbm_budget_bytes, allocated once by
+ * hawkes_serve_create (the only allocation; evaluation never allocates).  A
+ * scheduler thread admits submitted requests in arrival order while fewer
+ * than max_slots are in flight and the request's footprint
+ * (hawkes_serve_footprint) fits in the arena; admitted requests of the same
+ * (d, precision) form a batch that runs as one kernel launch per phase on one
+ * of several HIP streams, so batches overlap on the device and requests that
+ * arrive meanwhile are admitted as slots and memory free up.  A request's
+ * result is bitwise identical whether it runs alone or in any batch.
+ *
+ * Threading: every call may come from any host thread.  x and grad_x stay
+ * owned by the client and must stay alive until the request completes.
+ * ------------------------------------------------------------------------ */
+typedef struct hawkes_server hawkes_server_t;
+
+typedef struct {
+  int status;              /* HAWKES_OK, or the request's error (e.g. HAWKES_EDATA) */
+  double loglik;           /* ell */
+  double grad_params[6];   /* API order */
+  uint64_t t_submit_ns, t_admit_ns, t_start_ns, t_done_ns;   /* steady clock */
+} hawkes_result_t;
+
+typedef struct {
+  int64_t pending;             /* submitted, not yet admitted */
+  int64_t active;              /* admitted, not yet complete */
+  uint64_t batches_launched;
+  uint64_t requests_submitted;
+  uint64_t arena_bytes, arena_free_bytes;
+} hawkes_serve_stats_t;
+
+/* flags for hawkes_serve_create: low 8 bits = number of streams (0: 2, max 8);
+ * HAWKES_SERVE_SIMULATE runs the scheduler without a GPU (requests complete
+ * after a virtual delay with loglik 0), for testing admission and queueing. */
+#define HAWKES_SERVE_SIMULATE 0x100
+
+/* Device bytes one admitted request of (n, d, prec) holds (0 if invalid). */
+size_t hawkes_serve_footprint(int64_t n, int d, int prec);
+
+/* Create a server (allocates the arena, streams and pinned staging).
+ * EINVAL: max_slots outside [1, 1024] or budget below 1 MiB; EDEVICE: HIP failure. */
+int hawkes_serve_create(size_t hbm_budget_bytes, int max_slots, int flags, hawkes_server_t** out);
+
+/* Register a dataset's event times (device, n, sorted) for dimension d; the
+ * server keeps its own device copy.  Returns the dataset id. */
+int hawkes_serve_register(hawkes_server_t* s, const double* t /* device */, int64_t n, int d, int32_t* dataset_id);
+
+/* Queue one evaluation.  x: device n*d float64 of the registered dataset's n
+ * and d; grad_x: device n*d output or NULL.  Checked on the host: EPARAM for
+ * invalid parameters, ENOMEM if the footprint can never fit the arena, ESTATE
+ * for an unknown dataset or a server being destroyed.  Data errors (NaN in x)
+ * surface later as that request's result status only. */
+int hawkes_serve_submit(hawkes_server_t* s, int32_t dataset_id, const double* x /* device */,
+                        const hawkes_params_t* p /* host */, int prec, double* grad_x /* device or NULL */,
+                        uint64_t* ticket);
+
+/* HAWKES_EPENDING until done; then copies the result, forgets the ticket and
+ * returns HAWKES_OK.  ESTATE for an unknown (or already collected) ticket. */
+int hawkes_serve_poll(hawkes_server_t* s, uint64_t ticket, hawkes_result_t* out);
+
+/* Blocks until done (timeout_ns < 0: no limit); ETIMEOUT leaves it pending. */
+int hawkes_serve_wait(hawkes_server_t* s, uint64_t ticket, hawkes_result_t* out, int64_t timeout_ns);
+
+int hawkes_serve_stats(hawkes_server_t* s, hawkes_serve_stats_t* out);
+
+/* Stops admission of new submissions, drains every queued and in-flight
+ * request, and frees the server. */
+int hawkes_serve_destroy(hawkes_server_t* s);
+
 /* Human-readable text for a status code (static storage). */
 const char* hawkes_strerror(int status);
 

@@ -52,21 +52,35 @@ def lib():
     return _lib
 
 
+class ServeResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("loglik", ctypes.c_double), ("grad_params", ctypes.c_double * 6),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64), ("t_start_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int64), ("active", ctypes.c_int64), ("batches_launched", ctypes.c_uint64),
+                ("requests_submitted", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("arena_free_bytes", ctypes.c_uint64)]
+
+
+SERVE_SIMULATE = 0x100
+
+
 def _bind_serve(L):
-    if not hasattr(L, "hawkes_serve_create"):
-        return
     vp, ci, i64, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+    L.hawkes_serve_footprint.argtypes = [i64, ci, ci]
+    L.hawkes_serve_footprint.restype = ctypes.c_size_t
     L.hawkes_serve_create.argtypes = [ctypes.c_size_t, ci, ci, ctypes.POINTER(vp)]
     L.hawkes_serve_register.argtypes = [vp, vp, i64, ci, ctypes.POINTER(ctypes.c_int32)]
     L.hawkes_serve_submit.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(HawkesParams), ci, vp,
                                       ctypes.POINTER(u64)]
-    L.hawkes_serve_poll.argtypes = [vp, u64, vp]
-    L.hawkes_serve_wait.argtypes = [vp, u64, vp, i64]
+    L.hawkes_serve_poll.argtypes = [vp, u64, ctypes.POINTER(ServeResult)]
+    L.hawkes_serve_wait.argtypes = [vp, u64, ctypes.POINTER(ServeResult), i64]
+    L.hawkes_serve_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
     L.hawkes_serve_destroy.argtypes = [vp]
-    L.hawkes_serve_footprint.argtypes = [i64, ci, ci]
-    L.hawkes_serve_footprint.restype = ctypes.c_size_t
     for f in (L.hawkes_serve_create, L.hawkes_serve_register, L.hawkes_serve_submit, L.hawkes_serve_poll,
-              L.hawkes_serve_wait, L.hawkes_serve_destroy):
+              L.hawkes_serve_wait, L.hawkes_serve_stats, L.hawkes_serve_destroy):
         f.restype = ci
 
 

@@ -1,0 +1,106 @@
+"""Client of the continuous-batching server (C ABI hawkes_serve_*).
+
+The server runs in the library: a native scheduler thread admits requests by
+free slots and HBM footprint and launches batches on several HIP streams.
+This class only marshals arguments and keeps the client's device buffers alive
+until their requests complete.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import HawkesError, ServeResult, ServeStats
+from .api import _prec, params_struct
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes: int = 8 << 30, max_slots: int = 64, streams: int = 2,
+                 simulate: bool = False):
+        self._L = _lib.lib()
+        self._h = ctypes.c_void_p()
+        flags = (streams & 0xFF) | (_lib.SERVE_SIMULATE if simulate else 0)
+        st = self._L.hawkes_serve_create(int(hbm_budget_bytes), int(max_slots), flags, ctypes.byref(self._h))
+        if st != _lib.OK:
+            raise HawkesError(st, "hawkes_serve_create")
+        self.simulate = simulate
+        self._keep: dict[int, tuple] = {}
+        self._datasets: dict[int, tuple] = {}
+
+    @staticmethod
+    def footprint(n: int, d: int, prec="mixed") -> int:
+        return int(_lib.lib().hawkes_serve_footprint(int(n), int(d), _prec(prec)))
+
+    def register(self, t, d: int, n: int | None = None) -> int:
+        """t: device float64 tensor of sorted times (or, in simulate mode, any
+        object with a data pointer).  Returns the dataset id."""
+        ptr = t.data_ptr() if hasattr(t, "data_ptr") else int(t)
+        n = int(t.shape[0]) if n is None else int(n)
+        ds = ctypes.c_int32()
+        st = self._L.hawkes_serve_register(self._h, ptr, n, int(d), ctypes.byref(ds))
+        if st != _lib.OK:
+            raise HawkesError(st, "hawkes_serve_register")
+        self._datasets[ds.value] = (t, n, int(d))
+        return ds.value
+
+    def submit(self, dataset: int, x, params, prec="mixed", grad_x=None) -> int:
+        xp = x.data_ptr() if hasattr(x, "data_ptr") else int(x)
+        gp = (grad_x.data_ptr() if hasattr(grad_x, "data_ptr") else int(grad_x)) if grad_x is not None else None
+        ps = params_struct(params)
+        tk = ctypes.c_uint64()
+        st = self._L.hawkes_serve_submit(self._h, int(dataset), xp, ctypes.byref(ps), _prec(prec), gp,
+                                         ctypes.byref(tk))
+        if st != _lib.OK:
+            raise HawkesError(st, "hawkes_serve_submit")
+        self._keep[tk.value] = (x, grad_x)
+        return tk.value
+
+    @staticmethod
+    def _res(r: ServeResult) -> dict:
+        return {"status": r.status, "loglik": r.loglik, "grad_params": list(r.grad_params),
+                "t_submit_ns": r.t_submit_ns, "t_admit_ns": r.t_admit_ns, "t_start_ns": r.t_start_ns,
+                "t_done_ns": r.t_done_ns}
+
+    def poll(self, ticket: int):
+        r = ServeResult()
+        st = self._L.hawkes_serve_poll(self._h, int(ticket), ctypes.byref(r))
+        if st == _lib.EPENDING:
+            return None
+        if st != _lib.OK:
+            raise HawkesError(st, "hawkes_serve_poll")
+        self._keep.pop(ticket, None)
+        return self._res(r)
+
+    def wait(self, ticket: int, timeout_s: float | None = None) -> dict:
+        r = ServeResult()
+        to = -1 if timeout_s is None else int(timeout_s * 1e9)
+        st = self._L.hawkes_serve_wait(self._h, int(ticket), ctypes.byref(r), to)
+        if st != _lib.OK:
+            raise HawkesError(st, "hawkes_serve_wait")
+        self._keep.pop(ticket, None)
+        return self._res(r)
+
+    def stats(self) -> dict:
+        s = ServeStats()
+        st = self._L.hawkes_serve_stats(self._h, ctypes.byref(s))
+        if st != _lib.OK:
+            raise HawkesError(st, "hawkes_serve_stats")
+        return {k: getattr(s, k) for k, _ in ServeStats._fields_}
+
+    def close(self):
+        if self._h:
+            self._L.hawkes_serve_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

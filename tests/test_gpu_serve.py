@@ -1,0 +1,105 @@
+"""Serving on the GPU: every result identical alone and in the mix (bitwise),
+identical to the direct C ABI call, within tolerance of the oracle; a bad
+request fails alone; a short open-loop run completes without errors."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2010_02994_amd import _lib, api, workloads as W
+from paper_2010_02994_amd.serve import Server
+from tests.gpu_util import check, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+SIZES = [700, 1500, 3000, 5000, 2000, 12000]
+
+
+@pytest.fixture(scope="module")
+def data():
+    out = []
+    for k, n in enumerate(SIZES):
+        w = W.serving_dataset(k, n)
+        out.append((w, torch.tensor(w.x, device=DEV), torch.tensor(w.t, device=DEV)))
+    return out
+
+
+def _run_set(server, ids, data, reqs, together):
+    """reqs: list of (dataset index, prec).  Returns [(status, ll, gp, grad_x numpy)]."""
+    outs = [torch.full_like(data[k][1], float("nan")) for k, _ in reqs]
+    res = [None] * len(reqs)
+    if together:
+        tks = [server.submit(ids[k], data[k][1], data[k][0].params, prec=p, grad_x=outs[j])
+               for j, (k, p) in enumerate(reqs)]
+        for j, tk in enumerate(tks):
+            res[j] = server.wait(tk, 60)
+    else:
+        for j, (k, p) in enumerate(reqs):
+            res[j] = server.wait(server.submit(ids[k], data[k][1], data[k][0].params, prec=p, grad_x=outs[j]), 60)
+    torch.cuda.synchronize()
+    return [(r["status"], r["loglik"], np.array(r["grad_params"]), o.cpu().numpy()) for r, o in zip(res, outs)]
+
+
+def test_alone_vs_mix_bitwise_and_direct_call(data):
+    reqs = [(k, p) for k in range(len(SIZES)) for p in ("mixed", "fp64")]
+    with Server(hbm_budget_bytes=4 << 30, max_slots=64, streams=3) as s:
+        ids = [s.register(d[2], 2) for d in data]
+        say("case serve alone")
+        alone = _run_set(s, ids, data, reqs, together=False)
+        say("case serve mix")
+        mix = _run_set(s, ids, data, reqs, together=True)
+        st = s.stats()
+    assert st["batches_launched"] < len(reqs) * 2      # the mix shared batches
+    for (k, p), a, m in zip(reqs, alone, mix):
+        assert a[0] == 0 and m[0] == 0
+        assert a[1] == m[1] and np.array_equal(a[2], m[2]) and np.array_equal(a[3], m[3]), (k, p)
+        w, x, t = data[k]
+        ll, gx, gp = api.grad(x, t, w.params, prec=p)
+        assert ll == a[1] and np.array_equal(gp, a[2]) and np.array_equal(gx.cpu().numpy(), a[3]), (k, p)
+    for k in (0, 3):
+        w = data[k][0]
+        st_, ll_ref, gx_ref, gp_ref = oracle.loglik_grad(w.x, w.t, w.params, threads=True)
+        for p in ("mixed", "fp64"):
+            j = reqs.index((k, p))
+            check(p, alone[j][1], alone[j][3], alone[j][2], ll_ref, gx_ref, gp_ref, w.params, w.n, label=f"serve{k}")
+
+
+def test_bad_request_fails_alone(data):
+    with Server(hbm_budget_bytes=2 << 30, max_slots=16) as s:
+        ids = [s.register(d[2], 2) for d in data]
+        bad_x = data[2][1].clone()
+        bad_x[10, 0] = float("nan")
+        say("case serve failure isolation")
+        good = [s.submit(ids[k], data[k][1], data[k][0].params, prec="mixed") for k in (0, 1, 3)]
+        bad = s.submit(ids[2], bad_x, data[2][0].params, prec="mixed")
+        more = [s.submit(ids[k], data[k][1], data[k][0].params, prec="mixed") for k in (4, 5)]
+        rb = s.wait(bad, 60)
+        assert rb["status"] == _lib.EDATA
+        for tk, k in zip(good + more, (0, 1, 3, 4, 5)):
+            r = s.wait(tk, 60)
+            assert r["status"] == 0
+            ll = api.loglik(data[k][1], data[k][2], data[k][0].params, prec="mixed")
+            assert r["loglik"] == ll
+
+
+def test_tight_budget_still_completes(data):
+    foot = Server.footprint(12000, 2, "mixed")
+    with Server(hbm_budget_bytes=foot + (1 << 20), max_slots=8) as s:
+        ids = [s.register(d[2], 2) for d in data]
+        say("case serve tight budget")
+        tks = [s.submit(ids[k], data[k][1], data[k][0].params, prec="mixed") for k in range(len(SIZES))] * 1
+        res = [s.wait(tk, 60) for tk in tks]
+        assert all(r["status"] == 0 for r in res)
+        st = s.stats()
+        assert st["arena_free_bytes"] == st["arena_bytes"]
+
+
+def test_open_loop_short_run():
+    from paper_2010_02994_amd import loadgen
+    with Server(hbm_budget_bytes=16 << 30, max_slots=64, streams=2) as s:
+        say("case serve open loop")
+        chains = loadgen.Chains(s, count=16, lo=1e3, hi=2e4)
+        out = loadgen.run(s, chains, rate=200.0, n_requests=200, prec="mixed", warmup=20)
+    say(f"  open loop: {out}")
+    assert out["requests"] == 200 and out["errors"] == 0 and out["unfinished"] == 0
+    assert out["p50_ms"] > 0 and out["p99_ms"] >= out["p50_ms"]
