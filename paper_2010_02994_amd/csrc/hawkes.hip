@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 
 #include "../../include/hawkes.h"
 #include "hawkes_common.hpp"
@@ -18,7 +19,7 @@ constexpr double kShiftMixed = 120.0;       // base-2 shift of the mixed pass's 
 constexpr double kFloorMixed = -60.0;       // flag when lambda * 2^S < cmax * 2^-60
 constexpr double kFloorFp64 = -900.0;       // flag when lambda < cmax * 2^-900
 constexpr int kFixGrid = 256;
-constexpr int kTargetItems = 2048;
+constexpr int kTargetItems = 5120;
 constexpr int kNumStages = 12;
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -62,7 +63,7 @@ bool make_layout(int64_t n, int d, int prec, Layout& Lo) {
   Lo.off_rec = take(real * rw * (size_t)Lo.n_pad);
   Lo.off_first = take(sizeof(int) * (size_t)Lo.n_pad);
   Lo.off_ps = take(real * (size_t)Lo.n_pad);
-  Lo.off_prow = take(sizeof(double) * (size_t)Lo.items * std::max(6, d) * kBandRows);
+  Lo.off_prow = take(real * (size_t)Lo.items * std::max(6, d) * kBandRows);
   Lo.off_pcol = take(real * (size_t)Lo.nb * std::max(3, d) * Lo.n_pad);
   Lo.off_sums = take(sizeof(double) * 6 * (size_t)n);
   Lo.off_sigma = take(sizeof(double) * (size_t)n);
@@ -86,6 +87,20 @@ bool valid_params(const hawkes_params_t* p) {
   if (!(p->h > 0) || !(p->tau > 0) || !(p->omega > 0) || !(p->xi > 0)) return false;
   if (p->mu < 0 || p->theta < 0 || (p->mu == 0 && p->theta == 0)) return false;
   return true;
+}
+
+// Base-2 shift of the mixed pass.  In bandwidth units every accumulated
+// product is bounded: 2^(S-a r2) r2 <= 2^S 2/(e a ln 2) for a = mA or mG, and
+// 2^(S-w dt) dt <= 2^S/(e w ln 2); a tile sums at most 64 terms per row and a
+// column sum at most kWaves*64*kRowsPerLane terms (< 2^9).  S keeps all of
+// them below 2^127 with margin, and is at most 120.
+static double shift_for(const KParams& k) {
+  const double ln2 = std::log(2.0), e = std::exp(1.0);
+  const double bound_r = 2.0 / (e * std::min((double)k.mA, (double)k.mG) * ln2);
+  const double bound_t = 2.0 / (e * (double)k.mB * ln2);
+  const double bound_w = 1.0 / (e * (double)k.mW * ln2);
+  const double m = std::max({1.0, bound_r, bound_t, bound_w});
+  return std::floor(std::min(kShiftMixed, 117.0 - std::log2(m)));
 }
 
 KParams make_kparams(const Layout& Lo, const hawkes_params_t* p) {
@@ -119,13 +134,16 @@ KParams make_kparams(const Layout& Lo, const hawkes_params_t* p) {
   k.gamma = 0.5 / (k.h * k.h);
   k.itx2 = 1.0 / (k.tau_x * k.tau_x);
   k.ih2 = 1.0 / (k.h * k.h);
-  k.Ab = (float)(log2e * k.alpha);
-  k.Bt = (float)(log2e * k.beta);
-  k.Gs = (float)(log2e * k.gamma);
-  k.Ws = (float)(log2e * k.omega);
+  k.mA = (float)(0.5 * log2e);
+  k.mB = (float)(0.5 * log2e);
+  k.mG = (float)(0.5 * log2e * (k.tau_x / k.h) * (k.tau_x / k.h));
+  k.mW = (float)(log2e * k.omega * k.tau_t);
+  k.inv_tx = 1.0 / k.tau_x;
+  k.inv_tt = 1.0 / k.tau_t;
   k.mixed = Lo.mixed;
-  k.S = Lo.mixed ? (float)kShiftMixed : 0.f;
-  k.sigma_main = Lo.mixed ? -kShiftMixed * std::log(2.0) : 0.0;
+  const double S = Lo.mixed ? shift_for(k) : 0.0;
+  k.S = (float)S;
+  k.sigma_main = -S * std::log(2.0);
   k.flag_floor = Lo.mixed ? kFloorMixed : kFloorFp64;
   return k;
 }
@@ -152,7 +170,7 @@ ReqDesc make_desc(const Layout& Lo, const KParams& kp, const double* x, const do
   r.rec = at<void>(ws, Lo.off_rec);
   r.first = at<int>(ws, Lo.off_first);
   r.ps = at<void>(ws, Lo.off_ps);
-  r.prow = at<double>(ws, Lo.off_prow);
+  r.prow = at<void>(ws, Lo.off_prow);
   r.pcol = at<void>(ws, Lo.off_pcol);
   r.sums = at<double>(ws, Lo.off_sums);
   r.sigma = at<double>(ws, Lo.off_sigma);
@@ -188,7 +206,7 @@ static inline void mark(hipStream_t s, int stage) {
 template <int D, bool MIX>
 static void launch_phases(const ReqDesc* reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s) {
   mark(s, 0);
-  k_prep<D><<<nreq, 1024, 0, s>>>(reqs);
+  k_init<D><<<nreq, 1024, 0, s>>>(reqs);
   mark(s, 1);
   k_pack<D, MIX><<<g.pad_blocks, kEvBlock, 0, s>>>(reqs, nreq);
   mark(s, 2);

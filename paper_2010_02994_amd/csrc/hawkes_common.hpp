@@ -11,7 +11,7 @@ constexpr int kRowsPerLane = 2;         // rows each lane owns in the pair passe
 constexpr int kBandRows = kThreads * kRowsPerLane;  // rows per band (512)
 constexpr int kTile = 64;               // columns per tile (one wave width)
 constexpr int kMaxD = 8;
-constexpr int kFixSeg = 8;              // partner segments per flagged row in the fix-up kernels
+constexpr int kFixSeg = 16;             // partner segments per flagged row in the fix-up kernels
 constexpr int kEvBlock = 256;           // events per block of the per-event kernels
 
 // Plain pairs and 16-byte chunks (the HIP vector types cannot be used through
@@ -42,7 +42,12 @@ struct KParams {
   double alpha, beta, gamma;  // 1/(2 tau_x^2), 1/(2 tau_t^2), 1/(2 h^2)
   double itx2, ih2;           // 1/tau_x^2, 1/h^2
   // mixed path: base-2 exponent scales and the constant shift S
-  float Ab, Bt, Gs, Ws, S;    // log2(e)/(2 tau_x^2), log2(e)/(2 tau_t^2), log2(e)/(2 h^2), log2(e) omega, S
+  // The mixed path stores coordinates in units of tau_x and times in units of
+  // tau_t; in those units the base-2 exponents are
+  //   background  S - mA r2 - mB dt^2,   excitation  S - mG r2 - mW dt
+  // with mA = mB = log2(e)/2, mG = log2(e)/2 (tau_x/h)^2, mW = log2(e) omega tau_t.
+  float mA, mB, mG, mW, S;
+  double inv_tx, inv_tt;      // 1/tau_x, 1/tau_t (packing scales)
   double sigma_main;          // natural log of the scale the main pass sums carry (-S ln 2, or 0)
   double flag_floor;          // a row is recomputed when lambda~ < cmax * 2^flag_floor
 };
@@ -62,7 +67,7 @@ struct ReqDesc {
   void* rec;
   int* first;
   void* ps;
-  double* prow;
+  void* prow;       // row partials: float (mixed) or double
   void* pcol;
   double* sums;
   double* sigma;

@@ -97,80 +97,28 @@ __device__ __forceinline__ int find_req(const ReqDesc* __restrict__ reqs, int nr
 
 // ------------------------------------------------------------ prepare / pack
 
-// One workgroup of 1024 threads per request: validates the data, finds the
-// data center (mixed path) and t_N, and writes the work-item table of the
-// pair passes.  Items run band-major from the last (longest) band to the first.
+// One workgroup of 1024 threads per request: clears the status words, takes
+// the float32 origin of the mixed path (spatial midpoint of the first and last
+// events, temporal midpoint of the time range; any origin inside the data's
+// extent keeps the offsets within the range), t_N, and writes the work-item
+// table of the pair passes.  Items run band-major from the last (longest)
+// band to the first.  Data validation happens in k_pack.
 template <int D>
-__global__ void __launch_bounds__(1024) k_prep(const ReqDesc* __restrict__ reqs) {
+__global__ void __launch_bounds__(1024) k_init(const ReqDesc* __restrict__ reqs) {
   const ReqDesc& rq = reqs[blockIdx.x];
   const auto x = glb(rq.x);
   const auto t = glb(rq.t);
   const int n = rq.kp.n, nb = rq.kp.nb, L = rq.kp.L;
-  __shared__ double s_min[kMaxD + 1][16], s_max[kMaxD + 1][16];
-  __shared__ int s_bad[16];
   __shared__ int s_scan[1024];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  double mn[D + 1], mx[D + 1];
-#pragma unroll
-  for (int k = 0; k <= D; ++k) { mn[k] = INFINITY; mx[k] = -INFINITY; }
-  int bad = 0;
-  // four independent loads in flight per thread and iteration
-  for (int i0 = tid; i0 < n; i0 += 4 * 1024) {
-    double tv[4], tp[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + u * 1024;
-      tv[u] = i < n ? t[i] : 0.0;
-      tp[u] = (i < n && i > 0) ? t[i - 1] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + u * 1024;
-      if (i < n) {
-        if (!isfinite(tv[u]) || tv[u] < 0.0) bad = 1;
-        if (i > 0 && !(tv[u] >= tp[u])) bad = 1;
-        mn[D] = fmin(mn[D], tv[u]);
-        mx[D] = fmax(mx[D], tv[u]);
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          const double v = x[(int64_t)i * D + k];
-          if (!isfinite(v)) bad = 1;
-          mn[k] = fmin(mn[k], v);
-          mx[k] = fmax(mx[k], v);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k <= D; ++k) {
-    for (int off = 32; off > 0; off >>= 1) {
-      mn[k] = fmin(mn[k], __shfl_xor(mn[k], off));
-      mx[k] = fmax(mx[k], __shfl_xor(mx[k], off));
-    }
-  }
-  for (int off = 32; off > 0; off >>= 1) bad |= __shfl_xor(bad, off);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k <= D; ++k) { s_min[k][w] = mn[k]; s_max[k][w] = mx[k]; }
-    s_bad[w] = bad;
-  }
-  __syncthreads();
+  const int tid = threadIdx.x;
   if (tid == 0) {
-    int b = 0;
-    double a[D + 1], z[D + 1];
-    for (int k = 0; k <= D; ++k) { a[k] = INFINITY; z[k] = -INFINITY; }
-    for (int ww = 0; ww < 16; ++ww) {
-      b |= s_bad[ww];
-      for (int k = 0; k <= D; ++k) { a[k] = fmin(a[k], s_min[k][ww]); z[k] = fmax(z[k], s_max[k][ww]); }
-    }
-    glb(rq.status)[kStData] = b ? -3 : 0;
+    glb(rq.status)[kStData] = 0;
     glb(rq.status)[kStZero] = 0;
     glb(rq.status)[kStFlagCount] = 0;
-    glb(rq.dconst)[0] = t[n - 1];                       // t_N (largest time for sorted input)
-    for (int k = 0; k < D; ++k) glb(rq.dconst)[1 + k] = 0.5 * (a[k] + z[k]);
-    glb(rq.dconst)[1 + kMaxD] = 0.5 * (a[D] + z[D]);
+    glb(rq.dconst)[0] = t[n - 1];                       // t_N for sorted input
+    for (int k = 0; k < D; ++k) glb(rq.dconst)[1 + k] = 0.5 * (x[k] + x[(int64_t)(n - 1) * D + k]);
+    glb(rq.dconst)[1 + kMaxD] = 0.5 * (t[0] + t[n - 1]);
   }
-  // work items: chunks of band b = ceil(ntiles_b / L), bands in descending order
   const int per = (nb + 1023) / 1024;
   int local = 0;
   for (int q = 0; q < per; ++q) {
@@ -217,7 +165,7 @@ __global__ void __launch_bounds__(kEvBlock) k_pack(const ReqDesc* __restrict__ r
   const ReqDesc& rq = reqs[r];
   const int i = (blockIdx.x - rq.blk_pad) * kEvBlock + threadIdx.x;
   const int n = rq.kp.n;
-  if (i >= rq.kp.n_pad || glb(rq.status)[kStData] != 0) return;
+  if (i >= rq.kp.n_pad) return;
   const auto t = glb(rq.t);
   typename Tr::Rec rr;
 #pragma unroll
@@ -225,12 +173,16 @@ __global__ void __launch_bounds__(kEvBlock) k_pack(const ReqDesc* __restrict__ r
   int f = 0;
   if (i < n) {
     const double ti = t[i];
+    bool bad = !isfinite(ti) || ti < 0.0 || (i > 0 && !(ti >= t[i - 1]));
+#pragma unroll
+    for (int k = 0; k < D; ++k) bad = bad || !isfinite(glb(rq.x)[(int64_t)i * D + k]);
+    if (bad) atomicOr(rq.status + kStData, 1);   // rare path: generic address is fine
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       const double v = glb(rq.x)[(int64_t)i * D + k];
-      rr.v[k] = MIX ? Real(v - glb(rq.dconst)[1 + k]) : Real(v);
+      rr.v[k] = MIX ? Real((v - glb(rq.dconst)[1 + k]) * rq.kp.inv_tx) : Real(v);
     }
-    rr.v[D] = MIX ? Real(ti - glb(rq.dconst)[1 + kMaxD]) : Real(ti);
+    rr.v[D] = MIX ? Real((ti - glb(rq.dconst)[1 + kMaxD]) * rq.kp.inv_tt) : Real(ti);
     int lo = 0, hi = i;   // lower_bound of ti in t[0..i]
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
@@ -293,11 +245,9 @@ __device__ __forceinline__ void pass1_tile(Pass1Rows<D, MIX>& S, const typename 
   constexpr int R = kRowsPerLane;
   const int lane = threadIdx.x & 63;
   // base-2 (mixed) or natural (float64) exponent scales
-  const Real cb = MIX ? Real(kp.Ab) : Real(kp.alpha);
-  const Real ct = MIX ? Real(kp.Bt) : Real(kp.beta);
-  const Real cg = MIX ? Real(kp.Gs) : Real(kp.gamma);
-  const Real cw = MIX ? Real(kp.Ws) : Real(kp.omega);
-  const Real sh = MIX ? Real(kp.S) : Real(0);
+  static_assert(!MIX, "the float32 passes use the lane-rotation kernels");
+  const Real cb = Real(kp.alpha), ct = Real(kp.beta), cg = Real(kp.gamma), cw = Real(kp.omega);
+  const Real sh = Real(0);
 #pragma unroll 4
   for (int k = 0; k < 64; ++k) {
     const int c = lane ^ k;
@@ -423,7 +373,7 @@ __global__ void __launch_bounds__(kThreads) k_pass1(const ReqDesc* __restrict__ 
   for (int r = 0; r < R; ++r) {
     const int lr = wave * 64 * R + r * 64 + lane;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) glb(rq.prow)[((int64_t)item * 6 + q) * kBandRows + lr] = S.a[r][q];
+    for (int q = 0; q < 6; ++q) glb(static_cast<double*>(rq.prow))[((int64_t)item * 6 + q) * kBandRows + lr] = S.a[r][q];
   }
 }
 
@@ -450,11 +400,9 @@ __device__ __forceinline__ void pass2_tile(Pass2Rows<D, MIX>& S, const typename 
   using Real = typename Traits<D, MIX>::Real;
   constexpr int R = kRowsPerLane;
   const int lane = threadIdx.x & 63;
-  const Real cb = MIX ? Real(kp.Ab) : Real(kp.alpha);
-  const Real ct = MIX ? Real(kp.Bt) : Real(kp.beta);
-  const Real cg = MIX ? Real(kp.Gs) : Real(kp.gamma);
-  const Real cw = MIX ? Real(kp.Ws) : Real(kp.omega);
-  const Real sh = MIX ? Real(kp.S) : Real(0);
+  static_assert(!MIX, "the float32 passes use the lane-rotation kernels");
+  const Real cb = Real(kp.alpha), ct = Real(kp.beta), cg = Real(kp.gamma), cw = Real(kp.omega);
+  const Real sh = Real(0);
 #pragma unroll 4
   for (int k = 0; k < 64; ++k) {
     const int c = lane ^ k;
@@ -571,7 +519,7 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ 
   for (int r = 0; r < R; ++r) {
     const int lr = wave * 64 * R + r * 64 + lane;
 #pragma unroll
-    for (int q = 0; q < D; ++q) glb(rq.prow)[((int64_t)item * D + q) * kBandRows + lr] = S.g[r][q];
+    for (int q = 0; q < D; ++q) glb(static_cast<double*>(rq.prow))[((int64_t)item * D + q) * kBandRows + lr] = S.g[r][q];
   }
 }
 
@@ -593,7 +541,7 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
                                                  float* __restrict__ acc_w, int tile_base, const KParams& kp) {
   constexpr int R = kRowsPerLane;
   const int lane = threadIdx.x & 63;
-  const float cb = kp.Ab, ct = kp.Bt, cg = kp.Gs, cw = kp.Ws, sh = kp.S;
+  const float mA = kp.mA, mB = kp.mB, mG = kp.mG, mW = kp.mW, sh = kp.S;
   const typename Traits<D, true>::Rec* __restrict__ my = cols + lane;
   float aK = 0.f, aR = 0.f, aU = 0.f;
 #pragma unroll 8
@@ -609,26 +557,23 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
         r2 = dx * dx + r2;
       }
       const float dt = S.t[r] - col.v[D];
-      const float u = cb * r2;
-      const float v = ct * (dt * dt);
-      const float ys = cg * r2;
-      const float ws = cw * dt;
-      float eb = __builtin_amdgcn_exp2f((sh - u) - v);
-      float es = __builtin_amdgcn_exp2f((sh - ys) - ws);
+      const float dt2 = dt * dt;
+      float eb = __builtin_amdgcn_exp2f(__builtin_fmaf(-mB, dt2, __builtin_fmaf(-mA, r2, sh)));
+      float es = __builtin_amdgcn_exp2f(__builtin_fmaf(-mW, dt, __builtin_fmaf(-mG, r2, sh)));
       if (MASK) {
         const bool act = (tile_base + ((lane + k) & 63)) < S.first[r];
         eb = act ? eb : 0.f;
         es = act ? es : 0.f;
       }
       S.a[r][0] += eb;
-      S.a[r][1] = eb * u + S.a[r][1];
-      S.a[r][2] = eb * v + S.a[r][2];
+      S.a[r][1] = eb * r2 + S.a[r][1];
+      S.a[r][2] = eb * dt2 + S.a[r][2];
       S.a[r][3] += es;
-      S.a[r][4] = es * ys + S.a[r][4];
-      S.a[r][5] = es * ws + S.a[r][5];
+      S.a[r][4] = es * r2 + S.a[r][4];
+      S.a[r][5] = es * dt + S.a[r][5];
       cK += eb;
-      cR = eb * u + cR;
-      cU = eb * v + cU;
+      cR = eb * r2 + cR;
+      cU = eb * dt2 + cU;
     }
     aK = rol1(aK) + cK;
     aR = rol1(aR) + cR;
@@ -641,7 +586,7 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
 }
 
 template <int D>
-__global__ void __launch_bounds__(kThreads) k_pass1_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) k_pass1_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
   using Rec = typename Traits<D, true>::Rec;
   using Real = float;
   using ColT = float;
@@ -718,7 +663,8 @@ __global__ void __launch_bounds__(kThreads) k_pass1_mixed(const ReqDesc* __restr
   for (int r = 0; r < R; ++r) {
     const int lr = wave * 64 * R + r * 64 + lane;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) glb(rq.prow)[((int64_t)item * 6 + q) * kBandRows + lr] = S.acc[r][q];
+    for (int q = 0; q < 6; ++q)
+      glb(static_cast<float*>(rq.prow))[((int64_t)item * 6 + q) * kBandRows + lr] = (float)S.acc[r][q];
   }
 }
 
@@ -727,7 +673,7 @@ __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const ty
                                                  float* __restrict__ acc_w, int tile_base, const KParams& kp) {
   constexpr int R = kRowsPerLane;
   const int lane = threadIdx.x & 63;
-  const float cb = kp.Ab, ct = kp.Bt, cg = kp.Gs, cw = kp.Ws, sh = kp.S;
+  const float mA = kp.mA, mB = kp.mB, mG = kp.mG, mW = kp.mW, sh = kp.S;
   const typename Traits<D, true>::Rec* __restrict__ my = cols + lane;
   float ag[D];
 #pragma unroll
@@ -748,10 +694,8 @@ __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const ty
         r2 = dx[q] * dx[q] + r2;
       }
       const float dt = S.t[r] - col.v[D];
-      const float zb = (sh - cb * r2) - ct * (dt * dt);
-      const float zs = (sh - cg * r2) - cw * dt;
-      float eb = __builtin_amdgcn_exp2f(zb);
-      float es = __builtin_amdgcn_exp2f(zs);
+      float eb = __builtin_amdgcn_exp2f(__builtin_fmaf(-mB, dt * dt, __builtin_fmaf(-mA, r2, sh)));
+      float es = __builtin_amdgcn_exp2f(__builtin_fmaf(-mW, dt, __builtin_fmaf(-mG, r2, sh)));
       if (MASK) {
         const bool act = (tile_base + ((lane + k) & 63)) < S.first[r];
         eb = act ? eb : 0.f;
@@ -850,7 +794,8 @@ __global__ void __launch_bounds__(kThreads) k_pass2_mixed(const ReqDesc* __restr
   for (int r = 0; r < R; ++r) {
     const int lr = wave * 64 * R + r * 64 + lane;
 #pragma unroll
-    for (int q = 0; q < D; ++q) glb(rq.prow)[((int64_t)item * D + q) * kBandRows + lr] = S.acc[r][q];
+    for (int q = 0; q < D; ++q)
+      glb(static_cast<float*>(rq.prow))[((int64_t)item * D + q) * kBandRows + lr] = (float)S.acc[r][q];
   }
 }
 
@@ -876,9 +821,9 @@ __global__ void __launch_bounds__(kEvBlock) k_reduce1(const ReqDesc* __restrict_
     const IPair bi{glb(rq.band)[b].x, glb(rq.band)[b].y};
     double s[6] = {0, 0, 0, 0, 0, 0};
     for (int c = 0; c < bi.y; ++c) {
-      const auto p = glb(rq.prow) + (int64_t)(bi.x + c) * 6 * kBandRows + lr;
+      const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * 6 * kBandRows + lr;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) s[q] += p[(int64_t)q * kBandRows];
+      for (int q = 0; q < 6; ++q) s[q] += (double)p[(int64_t)q * kBandRows];
     }
     const auto pcol = glb(static_cast<const ColT*>(rq.pcol));
     for (int I = b; I < kp.nb; ++I) {
@@ -886,11 +831,11 @@ __global__ void __launch_bounds__(kEvBlock) k_reduce1(const ReqDesc* __restrict_
 #pragma unroll
       for (int q = 0; q < 3; ++q) s[q] += (double)p[(int64_t)q * kp.n_pad];
     }
-    if (MIX) {
-      s[1] /= (double)kp.Ab;
-      s[2] /= (double)kp.Bt;
-      s[4] /= (double)kp.Gs;
-      s[5] /= (double)kp.Ws;
+    if (MIX) {   // moments were accumulated in bandwidth units
+      s[1] *= kp.tau_x * kp.tau_x;
+      s[2] *= kp.tau_t * kp.tau_t;
+      s[4] *= kp.tau_x * kp.tau_x;
+      s[5] *= kp.tau_t;
     }
     const double lam = kp.cbg * s[0] + kp.cse * s[3];
     flag = !(lam >= kp.cmax * exp2(kp.flag_floor));
@@ -1073,8 +1018,9 @@ __global__ void __launch_bounds__(kEvBlock) k_final1(const ReqDesc* __restrict__
     v[7] = lt > 0.0 ? 0.0 : 1.0;
     glb(rq.logl)[i] = L;
     // pass-2 factors: 1/lambda scaled to the main pass's 2^S terms
-    const double pb = fl ? 0.0 : kp.cbg * kp.itx2 * il;
-    const double ps = fl ? 0.0 : kp.cse * kp.ih2 * il;
+    // mixed: coordinates are in units of tau_x, so one factor tau_x moves in
+    const double pb = fl ? 0.0 : (MIX ? kp.cbg * kp.inv_tx * il : kp.cbg * kp.itx2 * il);
+    const double ps = fl ? 0.0 : (MIX ? kp.cse * kp.tau_x * kp.ih2 * il : kp.cse * kp.ih2 * il);
     glb(static_cast<Rec*>(rq.rec))[i].v[D + 1] = (Real)pb;
     glb(static_cast<Real*>(rq.ps))[i] = (Real)ps;
   }
@@ -1103,7 +1049,7 @@ __global__ void __launch_bounds__(256) k_final2(const ReqDesc* __restrict__ reqs
     const auto out8 = glb(rq.out8);
     if (bad != 0) {
       for (int q = 0; q < 7; ++q) out8[q] = NAN;
-      out8[7] = (double)bad;
+      out8[7] = -3.0;   // HAWKES_EDATA
     } else if (v[7] > 0.0) {
       glb(rq.status)[kStZero] = 1;
       out8[0] = -INFINITY;
@@ -1216,9 +1162,9 @@ __global__ void __launch_bounds__(kEvBlock) k_reduce2(const ReqDesc* __restrict_
 #pragma unroll
   for (int q = 0; q < D; ++q) s[q] = 0.0;
   for (int c = 0; c < bi.y; ++c) {
-    const auto p = glb(rq.prow) + (int64_t)(bi.x + c) * D * kBandRows + lr;
+    const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * D * kBandRows + lr;
 #pragma unroll
-    for (int q = 0; q < D; ++q) s[q] += p[(int64_t)q * kBandRows];
+    for (int q = 0; q < D; ++q) s[q] += (double)p[(int64_t)q * kBandRows];
   }
   const auto pcol = glb(static_cast<const ColT*>(rq.pcol));
   for (int I = b; I < kp.nb; ++I) {
