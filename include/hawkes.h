@@ -79,7 +79,13 @@ int hawkes_loglik(const double* x, const double* t, int64_t n, int d, const hawk
 
 /* Log-likelihood and full gradient.  grad_x: device, n*d row-major, overwritten.
  * loglik (host, 1) and grad_params (host, 6, API order) receive the scalars;
- * either may be NULL.  Synchronizes the stream to deliver them. */
+ * either may be NULL.  Synchronizes the stream to deliver them.
+ * Gradient calls also use a library-owned side stream (non-blocking, default
+ * priority; one per concurrent caller, kept until the process ends): the
+ * float64 fix-ups and the finalize kernels run there while the gradient pass
+ * runs on `stream`, and `stream` waits for them before the last kernel, so to
+ * the caller all of the call's work is ordered on `stream`.  Calls on one
+ * stream must come from one thread at a time. */
 int hawkes_grad(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p /* host */,
                 int prec, void* ws, size_t ws_bytes, void* stream,
                 double* loglik /* host or NULL */, double* grad_x /* device */, double* grad_params /* host or NULL */);
@@ -94,7 +100,8 @@ int hawkes_grad_async(const double* x, const double* t, int64_t n, int d, const 
 
 /* hawkes_grad plus per-stage device durations: stage_ms (host, 12 floats)
  * receives the milliseconds between HIP events recorded on the call's stream
- * before and after each kernel, in launch order: prep, pack, pass1 (rates),
+ * before and after each kernel; every stage runs in order on that stream
+ * (no side stream), in launch order: prep, pack, pass1 (rates),
  * reduce1, flag list, fix-up 1, finalize, finalize reduction, pass2
  * (gradient), fix-up 2b, fix-up 2a, reduce2.  Used by the benchmark to price
  * each kernel against its roofline; the numerical results equal hawkes_grad's. */

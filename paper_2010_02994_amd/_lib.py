@@ -42,7 +42,9 @@ def lib():
         L.hawkes_loglik.argtypes = [dp, dp, i64, ci, pp, ci, vp, ctypes.c_size_t, vp, hd]
         L.hawkes_grad.argtypes = [dp, dp, i64, ci, pp, ci, vp, ctypes.c_size_t, vp, hd, dp, hd]
         L.hawkes_grad_async.argtypes = [dp, dp, i64, ci, pp, ci, vp, ctypes.c_size_t, vp, dp, dp]
-        for f in (L.hawkes_loglik, L.hawkes_grad, L.hawkes_grad_async):
+        L.hawkes_grad_timed.argtypes = [dp, dp, i64, ci, pp, ci, vp, ctypes.c_size_t, vp, hd, dp, hd,
+                                        ctypes.POINTER(ctypes.c_float)]
+        for f in (L.hawkes_loglik, L.hawkes_grad, L.hawkes_grad_async, L.hawkes_grad_timed):
             f.restype = ci
         L.hawkes_strerror.argtypes = [ci]
         L.hawkes_strerror.restype = ctypes.c_char_p

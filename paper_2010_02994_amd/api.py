@@ -37,13 +37,18 @@ _ws_cache: dict = {}
 
 
 def workspace(n: int, d: int, prec, device) -> torch.Tensor:
+    """Cached workspace, one per device and stream: calls on one stream run in
+    order, so they can share it (a stream must not be driven from two threads
+    at once).  It is allocated on that stream, so torch's caching allocator
+    only hands it out again behind the work queued there."""
     need = workspace_bytes(n, d, prec)
     if need == 0:
         raise HawkesError(_lib.EINVAL, "workspace size")
-    key = torch.device(device)
+    dev = torch.device(device)
+    key = (dev, _stream_ptr(dev))
     ws = _ws_cache.get(key)
     if ws is None or ws.numel() < need:
-        ws = torch.empty(need, dtype=torch.uint8, device=key)
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
         _ws_cache[key] = ws
     return ws
 

@@ -7,6 +7,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <vector>
 
 #include "../../include/hawkes.h"
 #include "hawkes_common.hpp"
@@ -92,15 +95,17 @@ bool valid_params(const hawkes_params_t* p) {
 // Base-2 shift of the mixed pass.  In bandwidth units every accumulated
 // product is bounded: 2^(S-a r2) r2 <= 2^S 2/(e a ln 2) for a = mA or mG, and
 // 2^(S-w dt) dt <= 2^S/(e w ln 2); a tile sums at most 64 terms per row and a
-// column sum at most kWaves*64*kRowsPerLane terms (< 2^9).  S keeps all of
-// them below 2^127 with margin, and is at most 120.
+// column sum at most kBandRows terms.  S keeps all of them below 2^127 with
+// margin, and is at most 120.
 static double shift_for(const KParams& k) {
   const double ln2 = std::log(2.0), e = std::exp(1.0);
   const double bound_r = 2.0 / (e * std::min((double)k.mA, (double)k.mG) * ln2);
   const double bound_t = 2.0 / (e * (double)k.mB * ln2);
   const double bound_w = 1.0 / (e * (double)k.mW * ln2);
   const double m = std::max({1.0, bound_r, bound_t, bound_w});
-  return std::floor(std::min(kShiftMixed, 117.0 - std::log2(m)));
+  // headroom: 2^127 max float, minus log2 of the largest term count (a band's rows)
+  const double terms = std::ceil(std::log2((double)kBandRows));
+  return std::floor(std::min(kShiftMixed, 126.0 - terms - std::log2(m)));
 }
 
 KParams make_kparams(const Layout& Lo, const hawkes_params_t* p) {
@@ -201,10 +206,64 @@ static inline void mark(hipStream_t s, int stage) {
   }
 }
 
-// The twelve phases over every request of a batch (all with the same D and
+// A side stream and two events.  In a gradient call the fix-up and finalize
+// kernels (flag list, fix1, final1, final2, fix2b, fix2a) run on the side
+// stream while pass 2 runs on the caller's stream: pass 2 reads nothing they
+// write, and k_reduce2, which reads both, waits for the side chain.
+struct Fork {
+  hipStream_t side;
+  hipEvent_t ready, done;
+};
+
+// Forks are held exclusively while a call enqueues (an event re-recorded by
+// another thread between record and wait would order the wrong work) and
+// returned afterwards; the stream work they ordered needs nothing more.  One
+// pool per device, grown on demand, kept for the life of the process.
+class ForkPool {
+ public:
+  Fork* take(int dev) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto& v = free_[dev];
+      if (!v.empty()) {
+        Fork* f = v.back();
+        v.pop_back();
+        return f;
+      }
+    }
+    Fork f{};
+    const bool s_ok = hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) == hipSuccess;
+    const bool r_ok = s_ok && hipEventCreateWithFlags(&f.ready, hipEventDisableTiming) == hipSuccess;
+    const bool d_ok = r_ok && hipEventCreateWithFlags(&f.done, hipEventDisableTiming) == hipSuccess;
+    if (!d_ok) {   // caller falls back to one stream
+      if (r_ok) (void)hipEventDestroy(f.ready);
+      if (s_ok) (void)hipStreamDestroy(f.side);
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return new Fork(f);
+  }
+  void give(int dev, Fork* f) {
+    std::lock_guard<std::mutex> lk(mu_);
+    free_[dev].push_back(f);
+  }
+
+ private:
+  std::mutex mu_;
+  std::map<int, std::vector<Fork*>> free_;
+};
+static ForkPool& fork_pool() {
+  static ForkPool* p = new ForkPool();   // never destroyed: streams outlive static destructors
+  return *p;
+}
+
+// The phases over every request of a batch (all with the same D and
 // precision).  reqs: device array of descriptors; totals: grid sizes.
+// fk == nullptr: everything in order on s (used when stages are timed).
 template <int D, bool MIX>
-static void launch_phases(const ReqDesc* reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s) {
+static bool launch_phases(const ReqDesc* reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s,
+                          const Fork* fk) {
+  bool ok = true;
   mark(s, 0);
   k_init<D><<<nreq, 1024, 0, s>>>(reqs);
   mark(s, 1);
@@ -213,51 +272,74 @@ static void launch_phases(const ReqDesc* reqs, int nreq, const BatchGrid& g, boo
   if constexpr (MIX) k_pass1_mixed<D><<<g.items, kThreads, 0, s>>>(reqs, nreq);
   else k_pass1<D, MIX><<<g.items, kThreads, 0, s>>>(reqs, nreq);
   mark(s, 3);
-  k_reduce1<MIX><<<g.ev_blocks, kEvBlock, 0, s>>>(reqs, nreq);
+  k_reduce1<D, MIX><<<g.ev_blocks, kRedThreads, 0, s>>>(reqs, nreq);
   mark(s, 4);
-  k_flaglist<<<nreq, 1024, 0, s>>>(reqs);
-  mark(s, 5);
-  k_fix1<D><<<dim3(kFixGrid, nreq), 256, 0, s>>>(reqs);
-  mark(s, 6);
-  k_final1<D, MIX><<<g.ev_blocks, kEvBlock, 0, s>>>(reqs, nreq);
-  mark(s, 7);
-  k_final2<<<nreq, 256, 0, s>>>(reqs);
-  mark(s, 8);
-  if (grad) {
-    if constexpr (MIX) k_pass2_mixed<D><<<g.items, kThreads, 0, s>>>(reqs, nreq);
-    else k_pass2<D, MIX><<<g.items, kThreads, 0, s>>>(reqs, nreq);
-    mark(s, 9);
+  const bool fork = grad && fk != nullptr;
+  hipStream_t a = s;   // stream of the fix-up and finalize chain
+  if (fork) {
+    ok = ok && hipEventRecord(fk->ready, s) == hipSuccess;
+    ok = ok && hipStreamWaitEvent(fk->side, fk->ready, 0) == hipSuccess;
+    a = fk->side;
+  }
+  k_flaglist<<<nreq, 1024, 0, a>>>(reqs);
+  mark(a, 5);
+  k_fix1<D><<<dim3(kFixGrid, nreq), 256, 0, a>>>(reqs);
+  mark(a, 6);
+  k_final1<D, MIX><<<g.ev_blocks, kEvBlock, 0, a>>>(reqs, nreq);
+  mark(a, 7);
+  k_final2<<<nreq, 256, 0, a>>>(reqs);
+  mark(a, 8);
+  if (!grad) return ok;
+  if (fork) {
+    k_fix2b<D><<<g.ev_blocks, kEvBlock, 0, a>>>(reqs, nreq);
+    k_fix2a<D><<<dim3(kFixGrid, nreq), 256, 0, a>>>(reqs);
+    ok = ok && hipEventRecord(fk->done, a) == hipSuccess;
+  }
+  if constexpr (MIX) k_pass2_mixed<D><<<g.items, kThreads, 0, s>>>(reqs, nreq);
+  else k_pass2<D, MIX><<<g.items, kThreads, 0, s>>>(reqs, nreq);
+  mark(s, 9);
+  if (fork) {
+    ok = ok && hipStreamWaitEvent(s, fk->done, 0) == hipSuccess;
+  } else {
     k_fix2b<D><<<g.ev_blocks, kEvBlock, 0, s>>>(reqs, nreq);
     mark(s, 10);
     k_fix2a<D><<<dim3(kFixGrid, nreq), 256, 0, s>>>(reqs);
     mark(s, 11);
-    k_reduce2<D, MIX><<<g.ev_blocks, kEvBlock, 0, s>>>(reqs, nreq);
-    mark(s, 12);
   }
+  k_reduce2<D, MIX><<<g.ev_blocks, kRedThreads, 0, s>>>(reqs, nreq);
+  mark(s, 12);
+  return ok;
 }
 
 template <bool MIX>
-static void dispatch_d(int d, const ReqDesc* reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s) {
+static bool dispatch_d(int d, const ReqDesc* reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s,
+                       const Fork* fk) {
   switch (d) {
-    case 1: launch_phases<1, MIX>(reqs, nreq, g, grad, s); break;
-    case 2: launch_phases<2, MIX>(reqs, nreq, g, grad, s); break;
-    case 3: launch_phases<3, MIX>(reqs, nreq, g, grad, s); break;
-    case 4: launch_phases<4, MIX>(reqs, nreq, g, grad, s); break;
-    case 5: launch_phases<5, MIX>(reqs, nreq, g, grad, s); break;
-    case 6: launch_phases<6, MIX>(reqs, nreq, g, grad, s); break;
-    case 7: launch_phases<7, MIX>(reqs, nreq, g, grad, s); break;
-    case 8: launch_phases<8, MIX>(reqs, nreq, g, grad, s); break;
+    case 1: return launch_phases<1, MIX>(reqs, nreq, g, grad, s, fk);
+    case 2: return launch_phases<2, MIX>(reqs, nreq, g, grad, s, fk);
+    case 3: return launch_phases<3, MIX>(reqs, nreq, g, grad, s, fk);
+    case 4: return launch_phases<4, MIX>(reqs, nreq, g, grad, s, fk);
+    case 5: return launch_phases<5, MIX>(reqs, nreq, g, grad, s, fk);
+    case 6: return launch_phases<6, MIX>(reqs, nreq, g, grad, s, fk);
+    case 7: return launch_phases<7, MIX>(reqs, nreq, g, grad, s, fk);
+    case 8: return launch_phases<8, MIX>(reqs, nreq, g, grad, s, fk);
   }
+  return false;
 }
 
 // Enqueue a batch whose descriptors already sit in device memory (block
-// offsets filled in).  Returns HAWKES_EDEVICE if a launch failed.
+// offsets filled in).  Gradient batches fork onto a side stream unless the
+// stages are being timed.  Returns HAWKES_EDEVICE if a launch failed.
 int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const BatchGrid& g, bool grad,
                  hipStream_t s) {
   (void)hipGetLastError();
-  if (mixed) dispatch_d<true>(d, dev_reqs, nreq, g, grad, s);
-  else dispatch_d<false>(d, dev_reqs, nreq, g, grad, s);
-  return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+  int dev = -1;
+  Fork* fk = nullptr;
+  if (grad && g_timer == nullptr && hipGetDevice(&dev) == hipSuccess) fk = fork_pool().take(dev);
+  const bool ok = mixed ? dispatch_d<true>(d, dev_reqs, nreq, g, grad, s, fk)
+                        : dispatch_d<false>(d, dev_reqs, nreq, g, grad, s, fk);
+  if (fk) fork_pool().give(dev, fk);
+  return ok && hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
 }
 
 // Fill the block offsets of descriptors [0, nreq) and return the grid sizes.
@@ -368,9 +450,18 @@ int hawkes_grad_timed(const double* x, const double* t, int64_t n, int d, const 
                       void* ws, size_t ws_bytes, void* stream, double* loglik, double* grad_x, double* grad_params,
                       float* stage_ms) {
   if (!stage_ms) return HAWKES_EINVAL;
-  hawkes::StageTimer tm;
-  for (int k = 0; k <= hawkes::kNumStages; ++k)
-    if (hipEventCreate(&tm.ev[k]) != hipSuccess) return HAWKES_EDEVICE;
+  // events are created once per thread and device and reused
+  static thread_local hawkes::StageTimer tm_cache[16];
+  static thread_local bool tm_ready[16] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return HAWKES_EDEVICE;
+  hawkes::StageTimer& tm = tm_cache[dev];
+  if (!tm_ready[dev]) {
+    for (int k = 0; k <= hawkes::kNumStages; ++k)
+      if (hipEventCreate(&tm.ev[k]) != hipSuccess) return HAWKES_EDEVICE;
+    tm_ready[dev] = true;
+  }
+  tm.used = 0;
   hawkes::g_timer = &tm;
   const int st = hawkes::run_sync(x, t, n, d, p, prec, ws, ws_bytes, stream, loglik, grad_x, grad_params);
   hawkes::g_timer = nullptr;
@@ -379,7 +470,6 @@ int hawkes_grad_timed(const double* x, const double* t, int64_t n, int d, const 
     hipEventSynchronize(tm.ev[tm.used - 1]);
     for (int k = 0; k + 1 < tm.used; ++k) hipEventElapsedTime(&stage_ms[k], tm.ev[k], tm.ev[k + 1]);
   }
-  for (int k = 0; k <= hawkes::kNumStages; ++k) hipEventDestroy(tm.ev[k]);
   return st;
 }
 

@@ -5,9 +5,23 @@
 
 namespace hawkes {
 
-constexpr int kWaves = 4;               // waves per workgroup
+// Pair-pass geometry: waves per workgroup and rows per lane (a band has
+// 64 * kWaves * kRowsPerLane rows).  Overridable at build time for tuning.
+#ifndef HK_WAVES
+#define HK_WAVES 4
+#endif
+#ifndef HK_ROWS_PER_LANE
+#define HK_ROWS_PER_LANE 2
+#endif
+#ifndef HK_RATE_WAVES_PER_EU
+#define HK_RATE_WAVES_PER_EU 5
+#endif
+#ifndef HK_GRAD_WAVES_PER_EU
+#define HK_GRAD_WAVES_PER_EU 7
+#endif
+constexpr int kWaves = HK_WAVES;        // waves per workgroup
 constexpr int kThreads = 64 * kWaves;   // workgroup size
-constexpr int kRowsPerLane = 2;         // rows each lane owns in the pair passes
+constexpr int kRowsPerLane = HK_ROWS_PER_LANE;  // rows each lane owns in the pair passes
 constexpr int kBandRows = kThreads * kRowsPerLane;  // rows per band (512)
 constexpr int kTile = 64;               // columns per tile (one wave width)
 constexpr int kMaxD = 8;

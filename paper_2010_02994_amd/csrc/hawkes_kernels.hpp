@@ -452,7 +452,7 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ 
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
   const int rid = find_req(reqs, nreq, blockIdx.x, 0);
   const ReqDesc& rq = reqs[rid];
-  if (uni(glb(rq.status)[kStData]) != 0 || uni(glb(rq.status)[kStZero]) != 0) return;
+  if (uni(glb(rq.status)[kStData]) != 0) return;
   const KParams& kp = rq.kp;
   const auto rec = glb(static_cast<const Rec*>(rq.rec));
   const auto first = glb(rq.first);
@@ -547,14 +547,14 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
 #pragma unroll 8
   for (int k = 0; k < 64; ++k) {
     const auto col = my[k];
-    float cK = 0.f, cR = 0.f, cU = 0.f;
+    float cK, cR, cU;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       float r2 = 0.f;
 #pragma unroll
       for (int q = 0; q < D; ++q) {
         const float dx = S.x[r][q] - col.v[q];
-        r2 = dx * dx + r2;
+        r2 = q == 0 ? dx * dx : dx * dx + r2;
       }
       const float dt = S.t[r] - col.v[D];
       const float dt2 = dt * dt;
@@ -571,9 +571,11 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
       S.a[r][3] += es;
       S.a[r][4] = es * r2 + S.a[r][4];
       S.a[r][5] = es * dt + S.a[r][5];
-      cK += eb;
-      cR = eb * r2 + cR;
-      cU = eb * dt2 + cU;
+      // column contributions summed over this lane's rows (no "+ 0": a signed
+      // zero keeps the compiler from folding it)
+      cK = r == 0 ? eb : cK + eb;
+      cR = r == 0 ? eb * r2 : eb * r2 + cR;
+      cU = r == 0 ? eb * dt2 : eb * dt2 + cU;
     }
     aK = rol1(aK) + cK;
     aR = rol1(aR) + cR;
@@ -586,7 +588,7 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
 }
 
 template <int D>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) k_pass1_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HK_RATE_WAVES_PER_EU))) k_pass1_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
   using Rec = typename Traits<D, true>::Rec;
   using Real = float;
   using ColT = float;
@@ -683,15 +685,13 @@ __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const ty
     const auto col = my[k];
     float cgr[D];
 #pragma unroll
-    for (int q = 0; q < D; ++q) cgr[q] = 0.f;
-#pragma unroll
     for (int r = 0; r < R; ++r) {
       float dx[D];
       float r2 = 0.f;
 #pragma unroll
       for (int q = 0; q < D; ++q) {
         dx[q] = S.x[r][q] - col.v[q];
-        r2 = dx[q] * dx[q] + r2;
+        r2 = q == 0 ? dx[q] * dx[q] : dx[q] * dx[q] + r2;
       }
       const float dt = S.t[r] - col.v[D];
       float eb = __builtin_amdgcn_exp2f(__builtin_fmaf(-mB, dt * dt, __builtin_fmaf(-mA, r2, sh)));
@@ -705,7 +705,7 @@ __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const ty
 #pragma unroll
       for (int q = 0; q < D; ++q) {
         S.g[r][q] = -coef * dx[q] + S.g[r][q];
-        cgr[q] = coef * dx[q] + cgr[q];
+        cgr[q] = r == 0 ? coef * dx[q] : coef * dx[q] + cgr[q];
       }
     }
 #pragma unroll
@@ -717,7 +717,7 @@ __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const ty
 }
 
 template <int D>
-__global__ void __launch_bounds__(kThreads) k_pass2_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HK_GRAD_WAVES_PER_EU))) k_pass2_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
   using Rec = typename Traits<D, true>::Rec;
   using Real = float;
   using ColT = float;
@@ -727,7 +727,7 @@ __global__ void __launch_bounds__(kThreads) k_pass2_mixed(const ReqDesc* __restr
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
   const int rid = find_req(reqs, nreq, blockIdx.x, 0);
   const ReqDesc& rq = reqs[rid];
-  if (uni(glb(rq.status)[kStData]) != 0 || uni(glb(rq.status)[kStZero]) != 0) return;
+  if (uni(glb(rq.status)[kStData]) != 0) return;
   const KParams& kp = rq.kp;
   const auto rec = glb(static_cast<const Rec*>(rq.rec));
   const auto first = glb(rq.first);
@@ -803,34 +803,55 @@ __global__ void __launch_bounds__(kThreads) k_pass2_mixed(const ReqDesc* __restr
 
 // Per event: fixed-order sum of the row partials (this band's items) and the
 // column partials (bands from this one to the last), conversion to the raw
-// sums K, R, U, J, V, W (times exp(sigma)), and the recompute flag.  Flagged
-// rows of each block are staged in index order for k_flaglist.
-template <bool MIX>
-__global__ void __launch_bounds__(kEvBlock) k_reduce1(const ReqDesc* __restrict__ reqs, int nreq) {
+// sums K, R, U, J, V, W (times exp(sigma)), the recompute flag, and the
+// pass-2 factors (1/lambda scaled to the main pass's terms; 0 for flagged rows,
+// whose pairs the float64 fix-ups take).  Pass 2 needs nothing later than this
+// kernel, so it can run while the fix-ups and the finalize kernels do.  Four lanes
+// share an event (each takes every fourth partial; the four partial sums are
+// combined by two butterfly steps, which gives every lane the same value; the
+// four lanes of an event always branch together), so the kernel keeps enough
+// loads in flight to stream the partial buffers.
+// Flagged rows of each block are staged in index order for k_flaglist.
+constexpr int kRedThreads = 4 * kEvBlock;
+
+__device__ __forceinline__ double quad_sum(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  return v;
+}
+
+template <int D, bool MIX>
+__global__ void __launch_bounds__(kRedThreads) k_reduce1(const ReqDesc* __restrict__ reqs, int nreq) {
   using ColT = typename std::conditional<MIX, float, double>::type;
-  __shared__ int s_cnt[kEvBlock / 64];
+  using Real = typename Traits<D, MIX>::Real;
+  using Rec = typename Traits<D, MIX>::Rec;
+  __shared__ int s_cnt[kRedThreads / 64];
   const int rid = find_req(reqs, nreq, blockIdx.x, 1);
   const ReqDesc& rq = reqs[rid];
-  if (glb(rq.status)[kStData] != 0) return;
+  if (uni(glb(rq.status)[kStData]) != 0) return;
   const KParams& kp = rq.kp;
   const int lb = blockIdx.x - rq.blk_ev;
-  const int i = lb * kEvBlock + threadIdx.x;
+  const int sub = threadIdx.x & 3;
+  const int i = lb * kEvBlock + (threadIdx.x >> 2);
   bool flag = false;
   if (i < kp.n) {
     const int b = i / kBandRows, lr = i % kBandRows;
     const IPair bi{glb(rq.band)[b].x, glb(rq.band)[b].y};
     double s[6] = {0, 0, 0, 0, 0, 0};
-    for (int c = 0; c < bi.y; ++c) {
+    for (int c = sub; c < bi.y; c += 4) {
       const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * 6 * kBandRows + lr;
 #pragma unroll
       for (int q = 0; q < 6; ++q) s[q] += (double)p[(int64_t)q * kBandRows];
     }
     const auto pcol = glb(static_cast<const ColT*>(rq.pcol));
-    for (int I = b; I < kp.nb; ++I) {
+#pragma unroll 4
+    for (int I = b + sub; I < kp.nb; I += 4) {
       const auto p = pcol + (int64_t)I * 3 * kp.n_pad + i;
 #pragma unroll
       for (int q = 0; q < 3; ++q) s[q] += (double)p[(int64_t)q * kp.n_pad];
     }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s[q] = quad_sum(s[q]);
     if (MIX) {   // moments were accumulated in bandwidth units
       s[1] *= kp.tau_x * kp.tau_x;
       s[2] *= kp.tau_t * kp.tau_t;
@@ -838,11 +859,20 @@ __global__ void __launch_bounds__(kEvBlock) k_reduce1(const ReqDesc* __restrict_
       s[5] *= kp.tau_t;
     }
     const double lam = kp.cbg * s[0] + kp.cse * s[3];
-    flag = !(lam >= kp.cmax * exp2(kp.flag_floor));
+    const bool fl = !(lam >= kp.cmax * exp2(kp.flag_floor));
+    flag = sub == 0 && fl;
+    if (sub == 0) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) glb(rq.sums)[(int64_t)i * 6 + q] = s[q];
-    glb(rq.sigma)[i] = kp.sigma_main;
-    glb(rq.flags)[i] = flag ? 1 : 0;
+      for (int q = 0; q < 6; ++q) glb(rq.sums)[(int64_t)i * 6 + q] = s[q];
+      glb(rq.sigma)[i] = kp.sigma_main;
+      glb(rq.flags)[i] = fl ? 1 : 0;
+      // mixed: coordinates are in units of tau_x, so one factor tau_x moves in
+      const double il = fl ? 0.0 : 1.0 / lam;
+      const double pb = MIX ? kp.cbg * kp.inv_tx * il : kp.cbg * kp.itx2 * il;
+      const double ps = MIX ? kp.cse * kp.tau_x * kp.ih2 * il : kp.cse * kp.ih2 * il;
+      glb(static_cast<Rec*>(rq.rec))[i].v[D + 1] = (Real)pb;
+      glb(static_cast<Real*>(rq.ps))[i] = (Real)ps;
+    }
   }
   // stage this block's flagged rows in index order (wave ballots, then waves in order)
   const unsigned long long m = __ballot(flag);
@@ -857,7 +887,7 @@ __global__ void __launch_bounds__(kEvBlock) k_reduce1(const ReqDesc* __restrict_
   }
   if (threadIdx.x == 0) {
     int tot = 0;
-    for (int ww = 0; ww < kEvBlock / 64; ++ww) tot += s_cnt[ww];
+    for (int ww = 0; ww < kRedThreads / 64; ++ww) tot += s_cnt[ww];
     glb(rq.bcount)[lb] = tot;
   }
 }
@@ -958,11 +988,9 @@ __device__ __forceinline__ double std_normal_cdf(double z) { return 0.5 * erfc(-
 __device__ __forceinline__ double std_normal_pdf(double z) { return 0.39894228040143267794 * exp(-0.5 * z * z); }
 
 // Per event: lambda, log lambda, compensator, log-likelihood term and the six
-// parameter-gradient terms; per-block fixed-order partials; the pass-2 factors.
+// parameter-gradient terms; per-block fixed-order partials.
 template <int D, bool MIX>
 __global__ void __launch_bounds__(kEvBlock) k_final1(const ReqDesc* __restrict__ reqs, int nreq) {
-  using Real = typename Traits<D, MIX>::Real;
-  using Rec = typename Traits<D, MIX>::Rec;
   __shared__ double sh[kEvBlock];
   const int rid = find_req(reqs, nreq, blockIdx.x, 1);
   const ReqDesc& rq = reqs[rid];
@@ -1017,12 +1045,6 @@ __global__ void __launch_bounds__(kEvBlock) k_final1(const ReqDesc* __restrict__
     v[6] = kp.cse * (s[4] / (kp.h * kp.h * kp.h) - D * s[3] / kp.h) * il;
     v[7] = lt > 0.0 ? 0.0 : 1.0;
     glb(rq.logl)[i] = L;
-    // pass-2 factors: 1/lambda scaled to the main pass's 2^S terms
-    // mixed: coordinates are in units of tau_x, so one factor tau_x moves in
-    const double pb = fl ? 0.0 : (MIX ? kp.cbg * kp.inv_tx * il : kp.cbg * kp.itx2 * il);
-    const double ps = fl ? 0.0 : (MIX ? kp.cse * kp.tau_x * kp.ih2 * il : kp.cse * kp.ih2 * il);
-    glb(static_cast<Rec*>(rq.rec))[i].v[D + 1] = (Real)pb;
-    glb(static_cast<Real*>(rq.ps))[i] = (Real)ps;
   }
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
@@ -1141,37 +1163,45 @@ __global__ void __launch_bounds__(256) k_fix2a(const ReqDesc* __restrict__ reqs)
   }
 }
 
-// grad_x = row partials + column partials + fix-up terms (fixed order).
+// grad_x = row partials + column partials + fix-up terms (fixed order; four
+// lanes per event as in k_reduce1).
 template <int D, bool MIX>
-__global__ void __launch_bounds__(kEvBlock) k_reduce2(const ReqDesc* __restrict__ reqs, int nreq) {
+__global__ void __launch_bounds__(kRedThreads) k_reduce2(const ReqDesc* __restrict__ reqs, int nreq) {
   using ColT = typename std::conditional<MIX, float, double>::type;
   const int rid = find_req(reqs, nreq, blockIdx.x, 1);
   const ReqDesc& rq = reqs[rid];
   const KParams& kp = rq.kp;
-  const int i = (blockIdx.x - rq.blk_ev) * kEvBlock + threadIdx.x;
-  if (i >= kp.n || glb(rq.status)[kStData] != 0 || rq.grad_x == nullptr) return;
+  const int sub = threadIdx.x & 3;
+  const int i = (blockIdx.x - rq.blk_ev) * kEvBlock + (threadIdx.x >> 2);
+  if (uni(glb(rq.status)[kStData]) != 0 || rq.grad_x == nullptr) return;
   const auto grad_x = glb(rq.grad_x);
-  if (glb(rq.status)[kStZero] != 0) {
+  if (uni(glb(rq.status)[kStZero]) != 0) {
+    if (i < kp.n && sub == 0)
 #pragma unroll
-    for (int q = 0; q < D; ++q) grad_x[(int64_t)i * D + q] = NAN;
+      for (int q = 0; q < D; ++q) grad_x[(int64_t)i * D + q] = NAN;
     return;
   }
-  const int b = i / kBandRows, lr = i % kBandRows;
-  const IPair bi{glb(rq.band)[b].x, glb(rq.band)[b].y};
+  if (i >= kp.n) return;   // the four lanes of an event leave together
   double s[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) s[q] = 0.0;
-  for (int c = 0; c < bi.y; ++c) {
+  const int b = i / kBandRows, lr = i % kBandRows;
+  const IPair bi{glb(rq.band)[b].x, glb(rq.band)[b].y};
+  for (int c = sub; c < bi.y; c += 4) {
     const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * D * kBandRows + lr;
 #pragma unroll
     for (int q = 0; q < D; ++q) s[q] += (double)p[(int64_t)q * kBandRows];
   }
   const auto pcol = glb(static_cast<const ColT*>(rq.pcol));
-  for (int I = b; I < kp.nb; ++I) {
+#pragma unroll 4
+  for (int I = b + sub; I < kp.nb; I += 4) {
     const auto p = pcol + (int64_t)I * D * kp.n_pad + i;
 #pragma unroll
     for (int q = 0; q < D; ++q) s[q] += (double)p[(int64_t)q * kp.n_pad];
   }
+#pragma unroll
+  for (int q = 0; q < D; ++q) s[q] = quad_sum(s[q]);
+  if (sub != 0) return;
 #pragma unroll
   for (int q = 0; q < D; ++q) s[q] += glb(rq.gfix)[(int64_t)i * D + q];
   if (glb(rq.flags)[i] != 0) {

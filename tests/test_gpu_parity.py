@@ -209,3 +209,73 @@ def test_invalid_inputs_return_status_and_leave_outputs():
         with pytest.raises(_lib.HawkesError) as e:
             api.grad(x, torch.tensor(t_ok, device="cuda:0"), badp)
         assert e.value.status == _lib.EPARAM
+
+
+def _grad_in_order(x_np, t_np, params, prec):
+    """The same evaluation through hawkes_grad_timed, which runs every stage in
+    order on the caller's stream (no side stream)."""
+    import ctypes
+    import torch
+    from paper_2010_02994_amd import _lib, api
+    x = torch.tensor(np.ascontiguousarray(x_np), device="cuda:0")
+    t = torch.tensor(np.ascontiguousarray(t_np), device="cuda:0")
+    n, d = x.shape
+    ws = api.workspace(n, d, prec, x.device)
+    gx = torch.empty_like(x)
+    ll = ctypes.c_double()
+    gp = (ctypes.c_double * 6)()
+    stage = (ctypes.c_float * 12)()
+    ps = api.params_struct(params)
+    st = _lib.lib().hawkes_grad_timed(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), api._prec(prec),
+                                      ws.data_ptr(), ws.numel(), api._stream_ptr(x.device), ctypes.byref(ll),
+                                      gx.data_ptr(), gp, stage)
+    assert st == 0, _lib.strerror(st)
+    return ll.value, gx.cpu().numpy(), np.array(gp[:])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_side_stream_matches_in_order(prec):
+    """hawkes_grad runs the fix-ups and finalize on a side stream during pass 2;
+    the results equal the all-in-order run bit for bit (flagged rows present)."""
+    x, t, p = _isolated_case()
+    say(f"case side-stream vs in-order prec={prec}")
+    a = run_gpu(x, t, p, prec)
+    b = _grad_in_order(x, t, p, prec)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_concurrent_callers_on_own_streams(prec):
+    """Four host threads, each on its own stream with its own data, call
+    hawkes_grad three times; every result equals a lone call's bit for bit."""
+    import threading
+    import torch
+    from paper_2010_02994_amd import api
+    cases = [W.random_case(60 + k, n, 2, ties=2, t_span=40.0) for k, n in enumerate((1500, 4000, 9000, 600))]
+    dev_in = [(torch.tensor(w.x, device="cuda:0"), torch.tensor(w.t, device="cuda:0")) for w in cases]
+    alone = [run_gpu(w.x, w.t, w.params, prec) for w in cases]
+    torch.cuda.synchronize()
+    out = [[None] * 3 for _ in cases]
+    errs = []
+
+    def worker(k):
+        try:
+            s = torch.cuda.Stream(device="cuda:0")
+            with torch.cuda.stream(s):
+                for r in range(3):
+                    ll, gx, gp = api.grad(dev_in[k][0], dev_in[k][1], cases[k].params, prec=prec)
+                    out[k][r] = (ll, gx.cpu().numpy(), gp)
+        except Exception as e:   # surfaced below
+            errs.append(repr(e))
+
+    say(f"case concurrent callers prec={prec}")
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(len(cases))]
+    for h in th:
+        h.start()
+    for h in th:
+        h.join(timeout=120)
+    assert not errs, errs
+    for k, w in enumerate(cases):
+        for r in range(3):
+            a, b = out[k][r], alone[k]
+            assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2]), (k, r)
