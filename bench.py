@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests per precision in the serving run (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--mwg-steps", type=int, default=3000,
+                    help="Metropolis-within-Gibbs location steps timed at one event per step (0 skips)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -171,6 +173,8 @@ def main():
     f2, e2 = pass_work(d, "pass2")
     path_work = pairs_u * (f1 + f2 + (e1 + e2) * FLOP_EQ_PER_EXP)
 
+    mwg = mwg_bench(w, dev, args.mwg_steps) if args.mwg_steps > 0 else None
+
     serve = None
     if args.serve_requests > 0:
         serve = serving(args.serve_requests, args.serve_rate)
@@ -192,9 +196,68 @@ def main():
                             "hawkes_grad, where flaglist..final2 and fix2b/fix2a overlap pass2 on a side stream",
            "fp64": fp64,
            "speedup_mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
+           "mwg": mwg,
            "serve": serve,
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
+
+
+def mwg_bench(w, dev, steps: int):
+    """Metropolis-within-Gibbs location updates on the same workload: each step
+    proposes new places for a block of latent events, uniform on each event's
+    disc around its observed location (an independence proposal, so the
+    threshold is log u), and is decided and applied on the device.  Steps are
+    enqueued back to back with no host synchronization; x and the cached
+    per-event terms stay resident in HBM."""
+    import torch
+    from paper_2010_02994_amd import _lib, api
+    rng = np.random.default_rng(7)
+    latent = np.flatnonzero(w.radius > 0)
+    x = torch.tensor(w.x, device=dev)
+    t = torch.tensor(w.t, device=dev)
+    out = {"workload": f"{w.name}: latent-disc location moves", "state": "fp64 per-event terms"}
+    for block, n_steps in ((1, steps), (64, max(1, steps // 6))):
+        terms, _ = api.event_terms(x, t, w.params, prec="fp64")
+        idx = np.sort(np.stack([rng.choice(latent, size=block, replace=False) for _ in range(n_steps)]), axis=1)
+        ang = rng.uniform(0, 2 * np.pi, idx.shape)
+        rad = w.radius[idx] * np.sqrt(rng.uniform(size=idx.shape))
+        xn = w.observed[idx] + np.stack([rad * np.cos(ang), rad * np.sin(ang)], axis=-1)
+        thr = np.log(rng.uniform(size=n_steps))
+        idx_d = torch.tensor(idx.astype(np.int64), device=dev)
+        xn_d = torch.tensor(xn, device=dev)
+        thr_d = torch.tensor(thr, device=dev)
+        outs = torch.empty((n_steps, 3), dtype=torch.float64, device=dev)
+        ws = api.mwg_workspace(w.n, dev)
+        # the C entry point straight from precomputed pointers, so host-side
+        # argument marshalling stays out of the device-bound loop
+        L = _lib.lib()
+        ps = api.params_struct(w.params)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        xp, tp, tmp, wp = x.data_ptr(), t.data_ptr(), terms.data_ptr(), ws.data_ptr()
+        ip, np_, hp, op = idx_d.data_ptr(), xn_d.data_ptr(), thr_d.data_ptr(), outs.data_ptr()
+
+        def step(s):
+            st = L.hawkes_mwg_step(xp, tp, w.n, w.d, ctypes.byref(ps), tmp, ip + s * block * 8,
+                                   np_ + s * block * w.d * 8, block, hp + s * 8, wp, ws.numel(), stream, op + s * 24)
+            assert st == 0, _lib.strerror(st)
+
+        warm = min(50, n_steps)
+        for s in range(warm):
+            step(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(warm, n_steps):
+            step(s)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        o = outs.cpu().numpy()
+        timed = n_steps - warm
+        out[f"block{block}"] = {"steps": timed, "us_per_step": el / max(timed, 1) * 1e6,
+                                "steps_per_s": timed / el if el > 0 else None,
+                                "pair_terms_per_step": block * (w.n - 1) * 2,
+                                "accept_rate": float(o[:, 1].mean()), "bad_status": int((o[:, 2] != 0).sum())}
+    x.copy_(torch.tensor(w.x, device=dev))
+    return out
 
 
 def serving(n_requests: int, rate: float):

@@ -110,6 +110,65 @@ int hawkes_grad_timed(const double* x, const double* t, int64_t n, int d, const 
                       double* loglik /* host or NULL */, double* grad_x /* device */,
                       double* grad_params /* host or NULL */, float* stage_ms /* host, 12 */);
 
+/* Per-event terms of the rate pass (Sec. 2.1) and the branching probability
+ * used to colour events in the influenza application (Sec. 4.3): the
+ * self-excitation share of the rate, xi(x_n, t_n) / lambda_n.  terms (device,
+ * n x 4 row-major float64) receives per event
+ *   [0] a_n = background rate at event n per unit mu0,
+ *   [1] b_n = self-excitation rate at event n per unit theta,
+ *   [2] log lambda_n, lambda_n = mu0 a_n + theta b_n (exact even where lambda_n
+ *       underflows float64; a_n and b_n are then 0),
+ *   [3] theta b_n / lambda_n.
+ * Runs the rate pass and finalize (no gradient pass); loglik (host or NULL)
+ * receives ell.  Synchronizes the stream.  Returns HAWKES_EZERORATE, with the
+ * terms written, when some lambda_n is 0. */
+int hawkes_event_terms(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p /* host */,
+                       int prec, void* ws, size_t ws_bytes, void* stream, double* terms /* device, n*4 */,
+                       double* loglik /* host or NULL */);
+
+/* ------------------------------------------------------------------------
+ * Metropolis-within-Gibbs location updates (Sec. 3: block-wise Metropolis
+ * moves of individual latent locations).  Moving the locations of a block of
+ * events changes each rate only through its pairs with the moved events and
+ * leaves every compensator term unchanged, so with the per-event terms of
+ * hawkes_event_terms cached, the change of the log-likelihood costs
+ * O(N * nmove) pair terms instead of a full O(N^2) pass.  All float64.
+ */
+
+/* Device workspace of hawkes_mwg_step for n events (0 if n is invalid). */
+size_t hawkes_mwg_workspace_bytes(int64_t n);
+
+/* One Metropolis step for the block of events idx[0..nmove) (device, int64,
+ * strictly increasing, each in [0, n)) proposed at x_new (device, nmove x d).
+ * Computes Delta ell = ell(x with the block moved) - ell(x) and accepts iff
+ * Delta ell > *log_thresh (device, 1 double), where the caller folds the
+ * uniform draw, the proposal ratio and the prior ratio into the threshold:
+ * log u - log q(x*|x) + log q(x|x*) - log p(x*) + log p(x).
+ * On accept the moved rows of x (device, n x d) are overwritten and terms
+ * (device, n x 4, from hawkes_event_terms with the same parameters, every
+ * lambda_n > 0) is updated in place; on reject nothing changes.
+ * out3 (device, 3 doubles) receives [Delta ell, accepted (0 or 1), status].
+ * Rows whose rate the move cancels to below 2^-26 of the terms it is formed
+ * from are recomputed exactly; other rows are updated incrementally, so after
+ * many accepted moves a periodic hawkes_event_terms refresh bounds the drift.
+ * Enqueue only: no host synchronization.  Host-side argument errors return at
+ * once; an invalid idx or non-finite x_new is reported in out3 (status
+ * HAWKES_EDATA, Delta ell NaN, rejected).  Calls sharing a workspace must be
+ * ordered on one stream. */
+int hawkes_mwg_step(double* x /* device, n*d */, const double* t, int64_t n, int d,
+                    const hawkes_params_t* p /* host */, double* terms /* device, n*4 */,
+                    const int64_t* idx /* device, nmove */, const double* x_new /* device, nmove*d */,
+                    int64_t nmove, const double* log_thresh /* device, 1 */, void* ws, size_t ws_bytes,
+                    void* stream, double* out3 /* device, 3 */);
+
+/* Log-likelihood at new weights mu0 = p->mu and theta = p->theta with every
+ * other parameter equal to those the terms were computed with (Sec. 2.1:
+ * lambda_n is linear in mu0 and theta, and so is Lambda_n), in O(N) from the
+ * cached terms.  out3 (device) receives [ell, d ell/d mu, d ell/d theta].
+ * Enqueue only. */
+int hawkes_loglik_reweight(const double* t, int64_t n, int d, const hawkes_params_t* p /* host */,
+                           const double* terms /* device, n*4 */, void* stream, double* out3 /* device, 3 */);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of evaluation requests from many HMC chains
  * (one request = one log-likelihood + gradient at new latent locations).

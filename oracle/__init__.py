@@ -113,3 +113,48 @@ def diagnostics(x, t, params, log_floor=float(np.log(np.finfo(np.float32).tiny))
     if st != 0:
         raise ValueError(f"oracle_diagnostics status {st}")
     return float(mn[0]), int(cnt[0])
+
+
+# ---------------------------------------------------------------------------
+# Per-event terms, Metropolis moves and reweighting, written from the
+# definitions above (Sec. 2.1 rates; Sec. 3 location updates; Sec. 4.3
+# branching probability).  Each is a plain composition of the rate and
+# log-likelihood routines, so it checks the incremental GPU path against a full
+# recomputation.
+
+def event_terms(x, t, params, threads: bool = True):
+    """(N, 4): background rate per unit mu0, self-excitation rate per unit
+    theta, log lambda, and theta * b / lambda (the self-excitation share of the
+    rate, i.e. the probability that the event has a parent)."""
+    p = np.asarray(params, dtype=np.float64)
+    lam, s6 = rates(x, t, p, threads=threads)
+    out = np.empty((lam.shape[0], 4))
+    out[:, 0] = s6[:, 0]
+    out[:, 1] = s6[:, 3]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        out[:, 2] = np.log(lam)
+        out[:, 3] = p[3] * s6[:, 3] / lam
+    return out
+
+
+def mwg_delta(x, t, params, idx, x_new, threads: bool = True):
+    """Change of the log-likelihood when the events idx move to x_new: the sum
+    over events of log(lambda_after / lambda_before), each rate recomputed in
+    full (the compensator does not involve locations).  Returns (delta, moved x)."""
+    import math
+    x = np.array(x, dtype=np.float64, copy=True)
+    if x.ndim == 1:
+        x = x[:, None]
+    lam0, _ = rates(x, t, params, threads=threads)
+    x1 = x.copy()
+    x1[np.asarray(idx, dtype=np.int64)] = np.asarray(x_new, dtype=np.float64).reshape(len(idx), x.shape[1])
+    lam1, _ = rates(x1, t, params, threads=threads)
+    with np.errstate(divide="ignore"):
+        delta = math.fsum(np.log(lam1) - np.log(lam0))
+    return delta, x1
+
+
+def loglik_reweight(x, t, params_new, threads: bool = True):
+    """(ell, d ell/d mu, d ell/d theta) at the given parameters."""
+    st, ll, _, gp = loglik_grad(x, t, params_new, threads=threads, want_grad_x=False)
+    return st, ll, float(gp[0]), float(gp[3])

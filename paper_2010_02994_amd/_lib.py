@@ -44,7 +44,13 @@ def lib():
         L.hawkes_grad_async.argtypes = [dp, dp, i64, ci, pp, ci, vp, ctypes.c_size_t, vp, dp, dp]
         L.hawkes_grad_timed.argtypes = [dp, dp, i64, ci, pp, ci, vp, ctypes.c_size_t, vp, hd, dp, hd,
                                         ctypes.POINTER(ctypes.c_float)]
-        for f in (L.hawkes_loglik, L.hawkes_grad, L.hawkes_grad_async, L.hawkes_grad_timed):
+        L.hawkes_event_terms.argtypes = [dp, dp, i64, ci, pp, ci, vp, ctypes.c_size_t, vp, dp, hd]
+        L.hawkes_mwg_workspace_bytes.argtypes = [i64]
+        L.hawkes_mwg_workspace_bytes.restype = ctypes.c_size_t
+        L.hawkes_mwg_step.argtypes = [dp, dp, i64, ci, pp, dp, vp, dp, i64, dp, vp, ctypes.c_size_t, vp, dp]
+        L.hawkes_loglik_reweight.argtypes = [dp, i64, ci, pp, dp, vp, dp]
+        for f in (L.hawkes_loglik, L.hawkes_grad, L.hawkes_grad_async, L.hawkes_grad_timed, L.hawkes_event_terms,
+                  L.hawkes_mwg_step, L.hawkes_loglik_reweight):
             f.restype = ci
         L.hawkes_strerror.argtypes = [ci]
         L.hawkes_strerror.restype = ctypes.c_char_p

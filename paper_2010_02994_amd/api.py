@@ -114,3 +114,82 @@ def grad_async(x: torch.Tensor, t: torch.Tensor, params, prec="mixed", out8: tor
     if st != _lib.OK:
         raise HawkesError(st, "hawkes_grad_async")
     return out8
+
+
+def event_terms(x: torch.Tensor, t: torch.Tensor, params, prec="fp64", out: torch.Tensor | None = None):
+    """Per-event terms (device (N, 4) float64: background rate per unit mu0,
+    self-excitation rate per unit theta, log lambda, branching probability)
+    and the log-likelihood.  Synchronizes the current stream."""
+    x, t = _check_inputs(x, t)
+    n, d = x.shape
+    ws = workspace(n, d, prec, x.device)
+    terms = out if out is not None else torch.empty((n, 4), dtype=torch.float64, device=x.device)
+    ll = ctypes.c_double(0.0)
+    ps = params_struct(params)
+    st = _lib.lib().hawkes_event_terms(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), _prec(prec),
+                                       ws.data_ptr(), ws.numel(), _stream_ptr(x.device), terms.data_ptr(),
+                                       ctypes.byref(ll))
+    if st not in (_lib.OK, _lib.EZERORATE):
+        raise HawkesError(st, "hawkes_event_terms")
+    return terms, ll.value
+
+
+_mwg_ws: dict = {}
+
+
+def mwg_workspace(n: int, device) -> torch.Tensor:
+    """Cached Metropolis-within-Gibbs workspace, one per device and stream."""
+    need = int(_lib.lib().hawkes_mwg_workspace_bytes(int(n)))
+    if need == 0:
+        raise HawkesError(_lib.EINVAL, "mwg workspace size")
+    dev = torch.device(device)
+    key = (dev, _stream_ptr(dev))
+    ws = _mwg_ws.get(key)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        _mwg_ws[key] = ws
+    return ws
+
+
+def mwg_step(x: torch.Tensor, t: torch.Tensor, params, terms: torch.Tensor, idx: torch.Tensor,
+             x_new: torch.Tensor, log_thresh: torch.Tensor, out3: torch.Tensor | None = None,
+             ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Enqueue one Metropolis step moving events idx (device int64, strictly
+    increasing) to x_new; x and terms are updated in place on accept.
+    Returns out3 (device): [Delta loglik, accepted, status]."""
+    if not (x.is_contiguous() and terms.is_contiguous() and x.dtype == torch.float64):
+        raise ValueError("x and terms must be contiguous float64 device tensors")
+    if idx.dtype != torch.int64 or x_new.dtype != torch.float64 or log_thresh.dtype != torch.float64:
+        raise ValueError("idx must be int64, x_new and log_thresh float64")
+    n, d = x.shape
+    if terms.shape != (n, 4) or x_new.shape != (idx.numel(), d) or log_thresh.numel() < 1:
+        raise ValueError("shape mismatch")
+    idx, x_new = idx.contiguous(), x_new.contiguous()
+    if ws is None:
+        ws = mwg_workspace(n, x.device)
+    if out3 is None:
+        out3 = torch.empty(3, dtype=torch.float64, device=x.device)
+    ps = params_struct(params)
+    st = _lib.lib().hawkes_mwg_step(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), terms.data_ptr(),
+                                    idx.data_ptr(), x_new.data_ptr(), idx.numel(), log_thresh.data_ptr(),
+                                    ws.data_ptr(), ws.numel(), _stream_ptr(x.device), out3.data_ptr())
+    if st != _lib.OK:
+        raise HawkesError(st, "hawkes_mwg_step")
+    return out3
+
+
+def loglik_reweight(t: torch.Tensor, d: int, params, terms: torch.Tensor,
+                    out3: torch.Tensor | None = None) -> torch.Tensor:
+    """Enqueue ell and its mu/theta derivatives at new weights from cached
+    terms (every other parameter as when the terms were computed)."""
+    n = t.numel()
+    if terms.shape != (n, 4) or not terms.is_contiguous():
+        raise ValueError("terms must be a contiguous (N, 4) tensor")
+    if out3 is None:
+        out3 = torch.empty(3, dtype=torch.float64, device=t.device)
+    ps = params_struct(params)
+    st = _lib.lib().hawkes_loglik_reweight(t.data_ptr(), n, d, ctypes.byref(ps), terms.data_ptr(),
+                                           _stream_ptr(t.device), out3.data_ptr())
+    if st != _lib.OK:
+        raise HawkesError(st, "hawkes_loglik_reweight")
+    return out3

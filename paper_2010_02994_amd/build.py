@@ -31,8 +31,7 @@ def _run(cmd):
 
 
 def build_library() -> str:
-    srcs = [os.path.join(CSRC, "hawkes.hip"), os.path.join(CSRC, "serve.hip")]
-    srcs = [s for s in srcs if os.path.exists(s)]
+    srcs = [os.path.join(CSRC, f) for f in ("hawkes.hip", "serve.hip", "mwg.hip")]
     tmp = LIB + ".tmp"
     _run([_hipcc(), *HIPFLAGS, "-fPIC", "-shared", "-lpthread", *srcs, "-o", tmp])
     os.replace(tmp, LIB)

@@ -367,7 +367,7 @@ static int check_args(const double* x, const double* t, int64_t n, int d, const 
 }
 
 int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
-              size_t ws_bytes, void* stream, double* out8, double* grad_x) {
+              size_t ws_bytes, void* stream, double* out8, double* grad_x, double* terms = nullptr) {
   Layout Lo;
   const int st = check_args(x, t, n, d, p, prec, ws, ws_bytes, Lo);
   if (st != HAWKES_OK) return st;
@@ -375,6 +375,7 @@ int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_p
   const KParams kp = make_kparams(Lo, p);
   hipStream_t s = static_cast<hipStream_t>(stream);
   ReqDesc desc = make_desc(Lo, kp, x, t, ws, out8, grad_x);
+  desc.terms = terms;
   const BatchGrid g = assign_blocks(&desc, 1);
   ReqDesc* dev = at<ReqDesc>(ws, Lo.off_desc);
   (void)hipGetLastError();
@@ -384,11 +385,12 @@ int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_p
 }
 
 static int run_sync(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
-                    size_t ws_bytes, void* stream, double* loglik, double* grad_x, double* grad_params) {
+                    size_t ws_bytes, void* stream, double* loglik, double* grad_x, double* grad_params,
+                    double* terms = nullptr) {
   Layout Lo;
   if (!ws || !make_layout(n, d, prec, Lo)) return HAWKES_EINVAL;
   double* out8 = at<double>(ws, Lo.off_out8);
-  int st = run_async(x, t, n, d, p, prec, ws, ws_bytes, stream, out8, grad_x);
+  int st = run_async(x, t, n, d, p, prec, ws, ws_bytes, stream, out8, grad_x, terms);
   if (st != HAWKES_OK) return st;
   double h[8];
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -421,6 +423,12 @@ int hawkes_grad(const double* x, const double* t, int64_t n, int d, const hawkes
                 size_t ws_bytes, void* stream, double* loglik, double* grad_x, double* grad_params) {
   if (!grad_x) return HAWKES_EINVAL;
   return hawkes::run_sync(x, t, n, d, p, prec, ws, ws_bytes, stream, loglik, grad_x, grad_params);
+}
+
+int hawkes_event_terms(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec,
+                       void* ws, size_t ws_bytes, void* stream, double* terms, double* loglik) {
+  if (!terms) return HAWKES_EINVAL;
+  return hawkes::run_sync(x, t, n, d, p, prec, ws, ws_bytes, stream, loglik, nullptr, nullptr, terms);
 }
 
 int hawkes_grad_async(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec,

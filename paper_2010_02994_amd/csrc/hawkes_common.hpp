@@ -94,6 +94,7 @@ struct ReqDesc {
   double* bpart;
   double* gfix;
   double* fixpart;
+  double* terms;    // optional, n x 4: per-event terms written by k_final1 (null: none)
   int blk_items;    // first block of this request in a pair-pass launch
   int blk_ev;       // first block in a per-event launch (kEvBlock events per block)
   int blk_pad;      // first block in the pack launch (n_pad / kEvBlock blocks)

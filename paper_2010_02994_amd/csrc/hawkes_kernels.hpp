@@ -1045,6 +1045,16 @@ __global__ void __launch_bounds__(kEvBlock) k_final1(const ReqDesc* __restrict__
     v[6] = kp.cse * (s[4] / (kp.h * kp.h * kp.h) - D * s[3] / kp.h) * il;
     v[7] = lt > 0.0 ? 0.0 : 1.0;
     glb(rq.logl)[i] = L;
+    if (rq.terms != nullptr) {
+      // background rate per unit mu0, self-excitation rate per unit theta,
+      // log lambda, and the probability that the event was triggered by an
+      // earlier one (self-excitation share of the rate)
+      const auto tp = glb(rq.terms) + (int64_t)i * 4;
+      tp[0] = s[0] > 0.0 ? exp(log(kp.cbg_unit * s[0]) + sg) : 0.0;
+      tp[1] = s[3] > 0.0 ? exp(log(kp.cse_unit * s[3]) + sg) : 0.0;
+      tp[2] = L;
+      tp[3] = kp.cse * s[3] * il;
+    }
   }
 #pragma unroll
   for (int q = 0; q < 8; ++q) {

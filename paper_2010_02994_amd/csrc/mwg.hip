@@ -1,0 +1,468 @@
+// libhawkes: Metropolis-within-Gibbs moves of event locations and reweighted
+// log-likelihoods, both O(N) given cached per-event terms (arXiv 2010.02994,
+// Sec. 3: block-wise Metropolis updates of individual location variables;
+// rates and compensator of Sec. 2.1).
+//
+// Cached state, n x 4 float64 per event (written by hawkes_event_terms):
+//   a_i  background rate at event i per unit mu0   (sum over j of the background pair term)
+//   b_i  self-excitation rate per unit theta        (sum over earlier j)
+//   L_i  log lambda_i, lambda_i = mu0 a_i + theta b_i
+//   p_i  theta b_i / lambda_i
+// Moving the locations of a block of events changes row i's rate only through
+// its pairs with the moved events, so Delta ell = sum_i log(lambda_i'/lambda_i)
+// costs O(N * block) plus one full O(N) row per moved event.  The compensator
+// does not depend on locations.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/hawkes.h"
+#include "hawkes_common.hpp"
+#include "hawkes_internal.hpp"
+
+namespace hawkes {
+namespace mwg {
+
+constexpr int kBlock = 256;
+constexpr int kSeg = 32;          // partner segments per exactly recomputed row
+constexpr int kExactGrid = 512;   // workgroups of the exact-row kernel (grid-stride over tasks)
+constexpr int kListThreads = 1024;
+
+struct Model {
+  double mu0, theta;
+  double cbg_unit, cse_unit;  // pair weights per unit mu0 / theta
+  double alpha, beta, gamma;  // 1/(2 tau_x^2), 1/(2 tau_t^2), 1/(2 h^2)
+  double omega;
+};
+
+struct Step {
+  Model m;
+  double* x;            // n x D, moved rows overwritten on accept
+  const double* t;
+  int n, nmove, nrb;    // events, moved events, row blocks
+  double* terms;        // n x 4 cached state
+  const int64_t* idx;   // nmove moved events, strictly increasing
+  const double* xnew;   // nmove x D proposed locations
+  const double* thresh; // accept iff Delta ell > *thresh
+  double* out3;         // [Delta ell, accepted, status]
+  // workspace
+  double* new_a;        // n each
+  double* new_b;
+  double* dlog;
+  int* flag;            // 0 incremental, 1 recompute exactly, 2 moved
+  double* bpart;        // nrb: per row block, sum of dlog over its incremental rows
+  int* bcount;          // nrb: rows of the block needing an exact recompute
+  int* stage;           // nrb x kBlock: those rows in index order
+  int* list;            // n: all of them in index order
+  double* part;         // n x kSeg x 2: segment sums (a, b) of each listed row
+  int* state;           // [accepted, list length]
+};
+
+// Contributions of event j to row i: background per unit mu0 (excluded at equal
+// times) and self-excitation per unit theta (only from strictly earlier j).
+template <int D>
+__device__ __forceinline__ void pair_ab(const Model& m, const double* xi, double ti, const double* xj, double tj,
+                                        double& a, double& b) {
+  double r2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const double dx = xi[q] - xj[q];
+    r2 = fma(dx, dx, r2);
+  }
+  const double dt = ti - tj;
+  a = dt != 0.0 ? m.cbg_unit * exp(-m.alpha * r2 - m.beta * dt * dt) : 0.0;
+  b = dt > 0.0 ? m.cse_unit * exp(-m.omega * dt - m.gamma * r2) : 0.0;
+}
+
+// Position of event j in the moved list, or -1 (binary search; the list is
+// read within its bounds whatever it holds).
+__device__ __forceinline__ int find_moved(const int64_t* idx, int nmove, int j) {
+  int lo = 0, hi = nmove - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int64_t v = idx[mid];
+    if (v == j) return mid;
+    if (v < j) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Rows not moved: the change of (a_i, b_i) from the moved events' old and new
+// places, and its log-rate change, summed per block in a fixed order.  When the
+// change cancels most of the rate (the new rate is below 2^-26 of the terms it
+// was formed from) the row is listed for an exact recompute instead, so float64
+// cancellation never decides a move.  Moved rows are listed too.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_mwg_rows(Step s) {
+  __shared__ double s_old[kBlock][D];
+  __shared__ double s_new[kBlock][D];
+  __shared__ double s_t[kBlock];
+  __shared__ int s_j[kBlock];
+  __shared__ double sh[kBlock];
+  __shared__ int s_wcnt[kBlock / 64];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const bool row = i < s.n;
+  double xi[D], ti = 0.0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) xi[q] = row ? s.x[(int64_t)i * D + q] : 0.0;
+  if (row) ti = s.t[i];
+  double da = 0.0, db = 0.0, oa = 0.0, ob = 0.0;
+  bool moved = false;
+  for (int c0 = 0; c0 < s.nmove; c0 += kBlock) {
+    const int cn = min(kBlock, s.nmove - c0);
+    __syncthreads();
+    if ((int)threadIdx.x < cn) {
+      const int64_t j = s.idx[c0 + threadIdx.x];
+      const bool ok = j >= 0 && j < s.n;
+      s_j[threadIdx.x] = ok ? (int)j : -1;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        s_old[threadIdx.x][q] = ok ? s.x[j * D + q] : 0.0;
+        s_new[threadIdx.x][q] = s.xnew[(int64_t)(c0 + threadIdx.x) * D + q];
+      }
+      s_t[threadIdx.x] = ok ? s.t[j] : 0.0;
+    }
+    __syncthreads();
+    if (row) {
+      for (int k = 0; k < cn; ++k) {
+        const int j = s_j[k];
+        if (j < 0) continue;
+        if (j == i) {
+          moved = true;
+          continue;
+        }
+        double a0, b0, a1, b1;
+        pair_ab<D>(s.m, xi, ti, s_old[k], s_t[k], a0, b0);
+        pair_ab<D>(s.m, xi, ti, s_new[k], s_t[k], a1, b1);
+        da += a1 - a0;
+        db += b1 - b0;
+        oa += a0;
+        ob += b0;
+      }
+    }
+  }
+  int fl = 0;
+  double dl = 0.0;
+  if (row) {
+    if (moved) {
+      fl = 2;
+    } else {
+      const double a = s.terms[(int64_t)i * 4 + 0], b = s.terms[(int64_t)i * 4 + 1];
+      const double na = a + da, nb = b + db;
+      const double lam = s.m.mu0 * a + s.m.theta * b;
+      const double lam1 = s.m.mu0 * na + s.m.theta * nb;
+      const double formed_from = lam + s.m.mu0 * oa + s.m.theta * ob;
+      fl = lam1 > 0x1p-26 * formed_from ? 0 : 1;
+      s.new_a[i] = na;
+      s.new_b[i] = nb;
+      if (fl == 0) dl = log1p((s.m.mu0 * da + s.m.theta * db) / lam);
+    }
+    s.flag[i] = fl;
+    s.dlog[i] = dl;
+  }
+  const double bs = block_sum(dl, sh);
+  // stage the rows needing an exact recompute, in index order
+  const bool listed = row && fl != 0;
+  const unsigned long long m = __ballot(listed);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) s_wcnt[w] = __popcll(m);
+  __syncthreads();
+  int before = 0, total = 0;
+  for (int ww = 0; ww < kBlock / 64; ++ww) {
+    if (ww < w) before += s_wcnt[ww];
+    total += s_wcnt[ww];
+  }
+  if (listed) s.stage[(int64_t)blockIdx.x * kBlock + before + __popcll(m & ((1ull << lane) - 1ull))] = i;
+  if (threadIdx.x == 0) {
+    s.bcount[blockIdx.x] = total;
+    s.bpart[blockIdx.x] = bs;
+  }
+}
+
+// One workgroup: scan of the per-block counts, then the listed rows in index order.
+__global__ void __launch_bounds__(kListThreads) k_mwg_list(Step s) {
+  __shared__ int s_scan[kListThreads];
+  const int tid = threadIdx.x;
+  const int per = (s.nrb + kListThreads - 1) / kListThreads;
+  const int lo = min(s.nrb, tid * per), hi = min(s.nrb, lo + per);
+  int cnt = 0;
+  for (int b = lo; b < hi; ++b) cnt += s.bcount[b];
+  s_scan[tid] = cnt;
+  __syncthreads();
+  for (int off = 1; off < kListThreads; off <<= 1) {
+    const int v = tid >= off ? s_scan[tid - off] : 0;
+    __syncthreads();
+    s_scan[tid] += v;
+    __syncthreads();
+  }
+  int pos = s_scan[tid] - cnt;
+  for (int b = lo; b < hi; ++b) {
+    const int c = s.bcount[b];
+    for (int k = 0; k < c; ++k) s.list[pos++] = s.stage[(int64_t)b * kBlock + k];
+  }
+  if (tid == kListThreads - 1) s.state[1] = s_scan[kListThreads - 1];
+}
+
+// Exact rows, split into (row, partner segment) tasks over a fixed grid: sums
+// of the row's pair terms against one segment of partners, every event at its
+// proposed place; a moved row sits at its proposed location.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_mwg_exact(Step s) {
+  __shared__ double sh[kBlock];
+  const int cnt = s.state[1];
+  const int seg = (s.n + kSeg - 1) / kSeg;
+  for (int64_t task = blockIdx.x; task < (int64_t)cnt * kSeg; task += gridDim.x) {
+    const int e = (int)(task / kSeg), sg = (int)(task % kSeg);
+    const int r = s.list[e];
+    const int rpos = s.flag[r] == 2 ? find_moved(s.idx, s.nmove, r) : -1;
+    double xr[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) xr[q] = rpos >= 0 ? s.xnew[(int64_t)rpos * D + q] : s.x[(int64_t)r * D + q];
+    const double tr = s.t[r];
+    const int j0 = sg * seg, j1 = min(s.n, j0 + seg);
+    double a = 0.0, b = 0.0;
+    for (int j = j0 + threadIdx.x; j < j1; j += kBlock) {
+      if (j == r) continue;
+      const int pos = find_moved(s.idx, s.nmove, j);
+      double xj[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) xj[q] = pos >= 0 ? s.xnew[(int64_t)pos * D + q] : s.x[(int64_t)j * D + q];
+      double pa, pb;
+      pair_ab<D>(s.m, xr, tr, xj, s.t[j], pa, pb);
+      a += pa;
+      b += pb;
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+      s.part[((int64_t)e * kSeg + sg) * 2 + 0] = a;
+      s.part[((int64_t)e * kSeg + sg) * 2 + 1] = b;
+    }
+  }
+}
+
+// One workgroup: checks the moved list, merges the exact rows' segments in a
+// fixed order, sums the log-rate changes in a fixed order, decides.
+__global__ void __launch_bounds__(kListThreads) k_mwg_decide(Step s, int D) {
+  __shared__ double sh[kListThreads];
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < s.nmove; k += kListThreads) {
+    const int64_t j = s.idx[k];
+    bool bad = j < 0 || j >= s.n || (k > 0 && s.idx[k - 1] >= j);
+    for (int q = 0; q < D; ++q) bad = bad || !isfinite(s.xnew[(int64_t)k * D + q]);
+    if (bad) atomicOr(&s_bad, 1);
+  }
+  const int cnt = s.state[1];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < cnt; e += kListThreads) {
+    const int r = s.list[e];
+    double a = 0.0, b = 0.0;
+    for (int sg = 0; sg < kSeg; ++sg) {
+      a += s.part[((int64_t)e * kSeg + sg) * 2 + 0];
+      b += s.part[((int64_t)e * kSeg + sg) * 2 + 1];
+    }
+    const double dl = log(s.m.mu0 * a + s.m.theta * b) - s.terms[(int64_t)r * 4 + 2];
+    s.new_a[r] = a;
+    s.new_b[r] = b;
+    s.dlog[r] = dl;
+    acc += dl;
+  }
+  for (int b = threadIdx.x; b < s.nrb; b += kListThreads) acc += s.bpart[b];
+  const double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    const bool bad = s_bad != 0;
+    const bool accept = !bad && tot > *s.thresh;
+    s.out3[0] = bad ? NAN : tot;
+    s.out3[1] = accept ? 1.0 : 0.0;
+    s.out3[2] = bad ? (double)HAWKES_EDATA : 0.0;
+    s.state[0] = accept ? 1 : 0;
+  }
+}
+
+// On accept: move the locations and refresh the cached terms of every row
+// that changed (untouched rows keep their bits).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_mwg_apply(Step s) {
+  if (s.state[0] == 0) return;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < s.nmove) {
+    const int64_t j = s.idx[i];
+#pragma unroll
+    for (int q = 0; q < D; ++q) s.x[j * D + q] = s.xnew[(int64_t)i * D + q];
+  }
+  if (i >= s.n) return;
+  double* tp = s.terms + (int64_t)i * 4;
+  const double na = s.new_a[i], nb = s.new_b[i];
+  if (s.flag[i] == 0 && na == tp[0] && nb == tp[1]) return;
+  const double lam1 = s.m.mu0 * na + s.m.theta * nb;
+  tp[0] = na;
+  tp[1] = nb;
+  tp[2] = tp[2] + s.dlog[i];
+  tp[3] = s.m.theta * nb / lam1;
+}
+
+// Log-likelihood and its derivatives in mu0 and theta at new weights, every
+// other parameter as when the terms were computed (one workgroup):
+//   ell = sum_i log(mu0 a_i + theta b_i) - sum_i (mu0 C_i + theta E_i)
+// with C_i the background's time integral and E_i = 1 - exp(-omega (T - t_i)).
+__global__ void __launch_bounds__(kListThreads) k_reweight(const double* t, int n, Model m, double tau_t,
+                                                             const double* terms, double* out3) {
+  __shared__ double sh[kListThreads];
+  const double T = t[n - 1];
+  double ll = 0.0, gm = 0.0, gt = 0.0;
+  for (int i = threadIdx.x; i < n; i += kListThreads) {
+    const double a = terms[(int64_t)i * 4 + 0], b = terms[(int64_t)i * 4 + 1];
+    const double lam = m.mu0 * a + m.theta * b;
+    const double ti = t[i];
+    const double za = (T - ti) / tau_t, zb = -ti / tau_t;
+    const double C = 0.5 * erfc(-za * 0.70710678118654752440) - 0.5 * erfc(-zb * 0.70710678118654752440);
+    const double E = -expm1(-m.omega * (T - ti));
+    ll += log(lam) - m.mu0 * C - m.theta * E;
+    gm += a / lam - C;
+    gt += b / lam - E;
+  }
+  ll = block_sum(ll, sh);
+  gm = block_sum(gm, sh);
+  gt = block_sum(gt, sh);
+  if (threadIdx.x == 0) {
+    out3[0] = ll;
+    out3[1] = gm;
+    out3[2] = gt;
+  }
+}
+
+static Model make_model(const hawkes_params_t* p, int d) {
+  const double two_pi = 6.283185307179586476925286766559;
+  Model m;
+  m.mu0 = p->mu;
+  m.theta = p->theta;
+  m.cbg_unit = std::pow(two_pi, -0.5 * (d + 1)) * std::pow(p->h, -d) / p->tau;
+  m.cse_unit = p->omega * std::pow(two_pi, -0.5 * d) * std::pow(p->xi, -d);
+  m.alpha = 0.5 / (p->h * p->h);
+  m.beta = 0.5 / (p->tau * p->tau);
+  m.gamma = 0.5 / (p->xi * p->xi);
+  m.omega = p->omega;
+  return m;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Workspace pieces for n events, in order.
+struct Pieces {
+  size_t new_a, new_b, dlog, flag, bpart, bcount, stage, list, part, state, total;
+};
+static Pieces pieces(int64_t n) {
+  const size_t nrb = (size_t)((n + kBlock - 1) / kBlock);
+  Pieces p;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+  p.new_a = take(sizeof(double) * (size_t)n);
+  p.new_b = take(sizeof(double) * (size_t)n);
+  p.dlog = take(sizeof(double) * (size_t)n);
+  p.flag = take(sizeof(int) * (size_t)n);
+  p.bpart = take(sizeof(double) * nrb);
+  p.bcount = take(sizeof(int) * nrb);
+  p.stage = take(sizeof(int) * nrb * kBlock);
+  p.list = take(sizeof(int) * (size_t)n);
+  p.part = take(sizeof(double) * 2 * kSeg * (size_t)n);
+  p.state = take(sizeof(int) * 16);
+  p.total = o;
+  return p;
+}
+
+template <int D>
+static void launch(const Step& s, hipStream_t st) {
+  k_mwg_rows<D><<<s.nrb, kBlock, 0, st>>>(s);
+  k_mwg_list<<<1, kListThreads, 0, st>>>(s);
+  k_mwg_exact<D><<<kExactGrid, kBlock, 0, st>>>(s);
+  k_mwg_decide<<<1, kListThreads, 0, st>>>(s, D);
+  k_mwg_apply<D><<<s.nrb, kBlock, 0, st>>>(s);
+}
+
+}  // namespace mwg
+}  // namespace hawkes
+
+extern "C" {
+
+size_t hawkes_mwg_workspace_bytes(int64_t n) {
+  if (n < 2 || n > (int64_t(1) << 30)) return 0;
+  return hawkes::mwg::pieces(n).total;
+}
+
+int hawkes_mwg_step(double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, double* terms,
+                    const int64_t* idx, const double* x_new, int64_t nmove, const double* log_thresh, void* ws,
+                    size_t ws_bytes, void* stream, double* out3) {
+  using namespace hawkes::mwg;
+  if (!x || !t || !p || !terms || !idx || !x_new || !log_thresh || !ws || !out3) return HAWKES_EINVAL;
+  if (d < 1 || d > hawkes::kMaxD || nmove < 1 || nmove > n) return HAWKES_EINVAL;
+  const size_t need = hawkes_mwg_workspace_bytes(n);
+  if (need == 0 || ws_bytes < need) return HAWKES_EINVAL;
+  if (!hawkes::valid_params(p)) return HAWKES_EPARAM;
+  const Pieces pc = pieces(n);
+  char* w = static_cast<char*>(ws);
+  Step s;
+  s.m = make_model(p, d);
+  s.x = x;
+  s.t = t;
+  s.n = (int)n;
+  s.nmove = (int)nmove;
+  s.nrb = (int)((n + kBlock - 1) / kBlock);
+  s.terms = terms;
+  s.idx = idx;
+  s.xnew = x_new;
+  s.thresh = log_thresh;
+  s.out3 = out3;
+  s.new_a = reinterpret_cast<double*>(w + pc.new_a);
+  s.new_b = reinterpret_cast<double*>(w + pc.new_b);
+  s.dlog = reinterpret_cast<double*>(w + pc.dlog);
+  s.flag = reinterpret_cast<int*>(w + pc.flag);
+  s.bpart = reinterpret_cast<double*>(w + pc.bpart);
+  s.bcount = reinterpret_cast<int*>(w + pc.bcount);
+  s.stage = reinterpret_cast<int*>(w + pc.stage);
+  s.list = reinterpret_cast<int*>(w + pc.list);
+  s.part = reinterpret_cast<double*>(w + pc.part);
+  s.state = reinterpret_cast<int*>(w + pc.state);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  switch (d) {
+    case 1: launch<1>(s, st); break;
+    case 2: launch<2>(s, st); break;
+    case 3: launch<3>(s, st); break;
+    case 4: launch<4>(s, st); break;
+    case 5: launch<5>(s, st); break;
+    case 6: launch<6>(s, st); break;
+    case 7: launch<7>(s, st); break;
+    case 8: launch<8>(s, st); break;
+  }
+  return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+}
+
+int hawkes_loglik_reweight(const double* t, int64_t n, int d, const hawkes_params_t* p, const double* terms,
+                           void* stream, double* out3) {
+  using namespace hawkes::mwg;
+  if (!t || !p || !terms || !out3 || n < 2 || n > (int64_t(1) << 30) || d < 1 || d > hawkes::kMaxD)
+    return HAWKES_EINVAL;
+  if (!hawkes::valid_params(p)) return HAWKES_EPARAM;
+  (void)hipGetLastError();
+  k_reweight<<<1, kListThreads, 0, static_cast<hipStream_t>(stream)>>>(t, (int)n, make_model(p, d), p->tau, terms,
+                                                                          out3);
+  return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+}
+
+}  // extern "C"

@@ -299,3 +299,109 @@ def test_threaded_build_is_bitwise_identical():
     a = oracle.loglik_grad(w.x[:300], w.t[:300], w.params)
     b = oracle.loglik_grad(w.x[:300], w.t[:300], w.params, threads=True)
     assert a[1] == b[1] and np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+# ------------------------------------- per-event terms and Metropolis moves ----
+
+def _two_events():
+    x = np.array([[0.3, -0.2], [0.1, 0.4]])
+    t = np.array([0.5, 1.7])
+    p = np.array([0.6, 0.9, 1.4, 0.5, 0.8, 0.7])
+    return x, t, p
+
+
+def _two_event_rates(x, t, p):
+    """lambda_1, lambda_2 and their parts from scipy densities (Sec. 2.1)."""
+    mu0, tx, tt, th, om, h = p
+    dx = x[1] - x[0]
+    dt = t[1] - t[0]
+    a = stats.multivariate_normal.pdf(np.r_[dx, dt], cov=np.diag([tx * tx, tx * tx, tt * tt]))
+    b2 = om * math.exp(-om * dt) * stats.multivariate_normal.pdf(dx, cov=h * h * np.eye(2))
+    return a, b2
+
+
+def test_event_terms_two_events_closed_form():
+    """a_n, b_n, log lambda_n and the branching probability for N = 2."""
+    x, t, p = _two_events()
+    a, b2 = _two_event_rates(x, t, p)
+    lam = [p[0] * a, p[0] * a + p[3] * b2]
+    ref = np.array([[a, 0.0, math.log(lam[0]), 0.0], [a, b2, math.log(lam[1]), p[3] * b2 / lam[1]]])
+    got = oracle.event_terms(x, t, p)
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_branching_probability_limits(d):
+    """theta = 0: no event has a parent; mu0 = 0: every event with an earlier
+    event is a child with probability 1."""
+    w = _case(70 + d, 30, d, ties=2, t_span=3.0)
+    p = w.params.copy()
+    p[3] = 0.0
+    assert np.all(oracle.event_terms(w.x, w.t, p)[:, 3] == 0.0)
+    p = w.params.copy()
+    p[0] = 0.0
+    got = oracle.event_terms(w.x, w.t, p)
+    later = w.t > w.t.min()
+    np.testing.assert_allclose(got[later, 3], 1.0, rtol=1e-15)
+
+
+@pytest.mark.parametrize("seed,block", [(81, [4]), (82, [0, 9, 10]), (83, [3, 17, 18, 40])])
+def test_mwg_delta_is_loglik_difference(seed, block):
+    """The incremental change equals ell(after) - ell(before) of the full
+    log-likelihood (whose compensator cancels), ties included."""
+    w = _case(seed, 60, 2, ties=3, t_span=6.0)
+    rng = np.random.default_rng(seed)
+    xn = w.x[block] + 0.4 * rng.standard_normal((len(block), 2))
+    delta, x1 = oracle.mwg_delta(w.x, w.t, w.params, block, xn)
+    _, l0, _, _ = oracle.loglik_grad(w.x, w.t, w.params)
+    _, l1, _, _ = oracle.loglik_grad(x1, w.t, w.params)
+    assert delta == pytest.approx(l1 - l0, rel=1e-11, abs=1e-11 * abs(l0))
+
+
+def test_mwg_delta_antisymmetric_and_additive():
+    w = _case(84, 50, 2, ties=2, t_span=5.0)
+    rng = np.random.default_rng(84)
+    y = w.x.copy()
+    y[[6, 11]] += 0.3 * rng.standard_normal((2, 2))
+    z = y.copy()
+    z[[11, 30]] += 0.3 * rng.standard_normal((2, 2))
+    d_xy, _ = oracle.mwg_delta(w.x, w.t, w.params, [6, 11], y[[6, 11]])
+    d_yx, _ = oracle.mwg_delta(y, w.t, w.params, [6, 11], w.x[[6, 11]])
+    d_yz, _ = oracle.mwg_delta(y, w.t, w.params, [11, 30], z[[11, 30]])
+    d_xz, _ = oracle.mwg_delta(w.x, w.t, w.params, [6, 11, 30], z[[6, 11, 30]])
+    assert d_xy == pytest.approx(-d_yx, rel=1e-12, abs=1e-13)
+    assert d_xy + d_yz == pytest.approx(d_xz, rel=1e-12, abs=1e-13)
+    d0, _ = oracle.mwg_delta(w.x, w.t, w.params, [6], w.x[[6]])
+    assert d0 == 0.0
+
+
+def test_mwg_delta_two_events_closed_form():
+    x, t, p = _two_events()
+    x1 = x.copy()
+    x1[1] = [0.9, -0.5]
+    a0, b0 = _two_event_rates(x, t, p)
+    a1, b1 = _two_event_rates(x1, t, p)
+    ref = (math.log(p[0] * a1) + math.log(p[0] * a1 + p[3] * b1)
+           - math.log(p[0] * a0) - math.log(p[0] * a0 + p[3] * b0))
+    delta, _ = oracle.mwg_delta(x, t, p, [1], x1[[1]])
+    assert delta == pytest.approx(ref, rel=1e-13)
+
+
+def test_reweight_is_linear_in_the_weights():
+    """ell at new (mu0, theta) rebuilt from the terms a_n, b_n and the
+    compensator (scipy normal cdf) equals the full log-likelihood there."""
+    w = _case(85, 40, 2, ties=2, t_span=4.0)
+    terms = oracle.event_terms(w.x, w.t, w.params)
+    p1 = w.params.copy()
+    p1[0] *= 1.7
+    p1[3] *= 0.4
+    T = w.t.max()
+    comp = (p1[0] * (stats.norm.cdf((T - w.t) / p1[2]) - stats.norm.cdf(-w.t / p1[2]))
+            + p1[3] * (1 - np.exp(-p1[4] * (T - w.t))))
+    ref = math.fsum(np.log(p1[0] * terms[:, 0] + p1[3] * terms[:, 1])) - math.fsum(comp)
+    st, ll, gm, gt = oracle.loglik_reweight(w.x, w.t, p1)
+    assert ll == pytest.approx(ref, rel=1e-12)
+    lam = p1[0] * terms[:, 0] + p1[3] * terms[:, 1]
+    cmu = stats.norm.cdf((T - w.t) / p1[2]) - stats.norm.cdf(-w.t / p1[2])
+    assert gm == pytest.approx(math.fsum(terms[:, 0] / lam) - math.fsum(cmu), rel=1e-10)
+    assert gt == pytest.approx(math.fsum(terms[:, 1] / lam) - math.fsum(1 - np.exp(-p1[4] * (T - w.t))), rel=1e-10)
