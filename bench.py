@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests per precision in the serving run (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--hmc-trajectories", type=int, default=3,
+                    help="timed 20-step device leapfrog trajectories on the gridded 10,000-event workload (0 skips)")
     ap.add_argument("--mwg-steps", type=int, default=3000,
                     help="Metropolis-within-Gibbs location steps timed at one event per step (0 skips)")
     args = ap.parse_args()
@@ -174,6 +176,7 @@ def main():
     path_work = pairs_u * (f1 + f2 + (e1 + e2) * FLOP_EQ_PER_EXP)
 
     mwg = mwg_bench(w, dev, args.mwg_steps) if args.mwg_steps > 0 else None
+    hmc = leapfrog_bench(dev, args.hmc_trajectories) if args.hmc_trajectories > 0 else None
 
     serve = None
     if args.serve_requests > 0:
@@ -197,6 +200,7 @@ def main():
            "fp64": fp64,
            "speedup_mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
            "mwg": mwg,
+           "hmc": hmc,
            "serve": serve,
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
@@ -257,6 +261,39 @@ def mwg_bench(w, dev, steps: int):
                                 "pair_terms_per_step": block * (w.n - 1) * 2,
                                 "accept_rate": float(o[:, 1].mean()), "bad_status": int((o[:, 2] != 0).sum())}
     x.copy_(torch.tensor(w.x, device=dev))
+    return out
+
+
+def leapfrog_bench(dev, trajectories: int):
+    """GPU-driven HMC trajectories on the gridded workload (N = 10,000, D = 2,
+    100 m cells): 20 leapfrog steps of 0.002 km, unit mass, momenta N(0, I),
+    positions reflected at the cell walls; every gradient is a full
+    evaluation, nothing returns to the host between steps."""
+    import torch
+    from paper_2010_02994_amd import api, workloads
+    w = workloads.config1(snapshots=0)
+    lo = torch.tensor(w.observed - 0.5 * w.cell, device=dev)
+    hi = torch.tensor(w.observed + 0.5 * w.cell, device=dev)
+    t = torch.tensor(w.t, device=dev)
+    rng = np.random.default_rng(11)
+    steps, eps = 20, 0.002
+    out = {"workload": f"{w.name}: 20-step leapfrog, reflecting cell walls", "steps": steps, "eps_km": eps}
+    for prec in ("mixed", "fp64"):
+        x = torch.tensor(w.x, device=dev)
+        p = torch.tensor(rng.standard_normal(w.x.shape), device=dev)
+        g, out8 = api.leapfrog(x, p, t, w.params, eps, steps, prec=prec, bound="box", b0=lo, b1=hi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(trajectories):
+            p.copy_(torch.tensor(rng.standard_normal(w.x.shape), device=dev))
+            g, out8 = api.leapfrog(x, p, t, w.params, eps, steps, prec=prec, bound="box", b0=lo, b1=hi,
+                                   grad_x=g, have_grad=True, out8=out8)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / trajectories
+        inside = bool(((x >= lo) & (x <= hi)).all().item())
+        out[prec] = {"ms_per_trajectory": el * 1e3, "ms_per_step": el * 1e3 / steps,
+                     "pair_interactions_per_s": steps * w.n * (w.n - 1) / el,
+                     "status": float(out8[7].item()), "inside_cells": inside}
     return out
 
 

@@ -170,6 +170,36 @@ int hawkes_loglik_reweight(const double* t, int64_t n, int d, const hawkes_param
                            const double* terms /* device, n*4 */, void* stream, double* out3 /* device, 3 */);
 
 /* ------------------------------------------------------------------------
+ * Hamiltonian Monte Carlo trajectories over the latent locations (Sec. 3:
+ * leapfrog with unit mass; Sec. 2.2: each location confined to a box or a
+ * disc around its observed position).  A wall mirrors the motion: in a box
+ * the momentum component normal to the wall changes sign; on a disc (a ball
+ * when d > 2) the momentum is reflected about the normal at the contact point.
+ */
+typedef enum {
+  HAWKES_BOUND_NONE = 0,  /* unconstrained */
+  HAWKES_BOUND_BOX = 1,   /* b0 = lower corners (n x d), b1 = upper corners (n x d); equal bounds pin the coordinate */
+  HAWKES_BOUND_DISC = 2   /* b0 = centres (n x d), b1 = radii (n); radius 0 pins the location */
+} hawkes_bound_t;
+
+/* `steps` leapfrog steps of size eps for the potential -ell(x):
+ *   p += eps/2 grad_x ell;  repeat { x flies for time eps with reflections;
+ *   p += eps grad_x ell (eps/2 after the last flight) }.
+ * x, p (device, n x d) are updated in place.  grad_x (device, n x d) holds
+ * grad_x ell at the entry x when have_grad != 0 (else it is computed first) and
+ * receives the gradient at the final x, so consecutive trajectories can chain.
+ * out8 (device) receives the final evaluation's [ell, 6 parameter gradients,
+ * status].  Every gradient is a full evaluation at precision prec enqueued on
+ * `stream`; no host synchronization.  ws: as for hawkes_grad.  The locations
+ * must start inside their bounds.  A flight that meets more than 64 disc walls
+ * stops at the wall.  Host-side argument errors return at once. */
+int hawkes_leapfrog(double* x /* device, n*d */, double* p /* device, n*d */, const double* t, int64_t n, int d,
+                    const hawkes_params_t* prm /* host */, int prec, double eps, int steps, int bound,
+                    const double* b0 /* device or NULL */, const double* b1 /* device or NULL */, void* ws,
+                    size_t ws_bytes, void* stream, double* grad_x /* device, n*d */, int have_grad,
+                    double* out8 /* device, 8 */);
+
+/* ------------------------------------------------------------------------
  * Serving: continuous batching of evaluation requests from many HMC chains
  * (one request = one log-likelihood + gradient at new latent locations).
  *

@@ -49,8 +49,10 @@ def lib():
         L.hawkes_mwg_workspace_bytes.restype = ctypes.c_size_t
         L.hawkes_mwg_step.argtypes = [dp, dp, i64, ci, pp, dp, vp, dp, i64, dp, vp, ctypes.c_size_t, vp, dp]
         L.hawkes_loglik_reweight.argtypes = [dp, i64, ci, pp, dp, vp, dp]
+        L.hawkes_leapfrog.argtypes = [dp, dp, dp, i64, ci, pp, ci, ctypes.c_double, ci, ci, dp, dp, vp,
+                                      ctypes.c_size_t, vp, dp, ci, dp]
         for f in (L.hawkes_loglik, L.hawkes_grad, L.hawkes_grad_async, L.hawkes_grad_timed, L.hawkes_event_terms,
-                  L.hawkes_mwg_step, L.hawkes_loglik_reweight):
+                  L.hawkes_mwg_step, L.hawkes_loglik_reweight, L.hawkes_leapfrog):
             f.restype = ci
         L.hawkes_strerror.argtypes = [ci]
         L.hawkes_strerror.restype = ctypes.c_char_p
@@ -73,6 +75,7 @@ class ServeStats(ctypes.Structure):
 
 
 SERVE_SIMULATE = 0x100
+BOUND_NONE, BOUND_BOX, BOUND_DISC = 0, 1, 2
 
 
 def _bind_serve(L):

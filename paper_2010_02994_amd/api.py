@@ -193,3 +193,43 @@ def loglik_reweight(t: torch.Tensor, d: int, params, terms: torch.Tensor,
     if st != _lib.OK:
         raise HawkesError(st, "hawkes_loglik_reweight")
     return out3
+
+
+_BOUNDS = {None: _lib.BOUND_NONE, "none": _lib.BOUND_NONE, "box": _lib.BOUND_BOX, "disc": _lib.BOUND_DISC}
+
+
+def leapfrog(x: torch.Tensor, p: torch.Tensor, t: torch.Tensor, params, eps: float, steps: int, prec="mixed",
+             bound=None, b0: torch.Tensor | None = None, b1: torch.Tensor | None = None,
+             grad_x: torch.Tensor | None = None, have_grad: bool = False, out8: torch.Tensor | None = None):
+    """Enqueue `steps` leapfrog steps on the current stream; x and p (device
+    (N, D) float64, contiguous) move in place.  bound: None, "box" (b0/b1 =
+    lower/upper corners) or "disc" (b0 = centres, b1 = radii).  Returns
+    (grad_x at the final x, out8 = [loglik, 6 parameter gradients, status])."""
+    if not (x.is_contiguous() and p.is_contiguous() and x.dtype == torch.float64 and p.dtype == torch.float64):
+        raise ValueError("x and p must be contiguous float64 device tensors")
+    n, d = x.shape
+    if p.shape != x.shape or t.shape != (n,):
+        raise ValueError("shape mismatch")
+    kind = _BOUNDS[bound]
+    if kind != _lib.BOUND_NONE:
+        if b0 is None or b1 is None:
+            raise ValueError("bounds need b0 and b1")
+        b0, b1 = b0.contiguous(), b1.contiguous()
+        want1 = (n, d) if kind == _lib.BOUND_BOX else (n,)
+        if b0.shape != (n, d) or b1.shape != want1:
+            raise ValueError("bound shape mismatch")
+    ws = workspace(n, d, prec, x.device)
+    if grad_x is None:
+        grad_x = torch.empty_like(x)
+        have_grad = False
+    if out8 is None:
+        out8 = torch.empty(8, dtype=torch.float64, device=x.device)
+    ps = params_struct(params)
+    st = _lib.lib().hawkes_leapfrog(x.data_ptr(), p.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), _prec(prec),
+                                    float(eps), int(steps), kind, b0.data_ptr() if b0 is not None else None,
+                                    b1.data_ptr() if b1 is not None else None, ws.data_ptr(), ws.numel(),
+                                    _stream_ptr(x.device), grad_x.data_ptr(), 1 if have_grad else 0,
+                                    out8.data_ptr())
+    if st != _lib.OK:
+        raise HawkesError(st, "hawkes_leapfrog")
+    return grad_x, out8

@@ -367,7 +367,7 @@ static int check_args(const double* x, const double* t, int64_t n, int d, const 
 }
 
 int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
-              size_t ws_bytes, void* stream, double* out8, double* grad_x, double* terms = nullptr) {
+              size_t ws_bytes, void* stream, double* out8, double* grad_x, double* terms) {
   Layout Lo;
   const int st = check_args(x, t, n, d, p, prec, ws, ws_bytes, Lo);
   if (st != HAWKES_OK) return st;

@@ -33,5 +33,9 @@ ReqDesc make_desc(const Layout& Lo, const KParams& kp, const double* x, const do
                   double* grad_x);
 BatchGrid assign_blocks(ReqDesc* descs, int nreq);
 int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s);
+// Enqueue one full evaluation (validation, rate pass, finalize and, when
+// grad_x is not null, the gradient pass) with no host synchronization.
+int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
+              size_t ws_bytes, void* stream, double* out8, double* grad_x, double* terms = nullptr);
 
 }  // namespace hawkes

@@ -1,0 +1,100 @@
+"""GPU parity of the device-resident leapfrog trajectories (reflecting box and
+disc walls) against the oracle's trajectories."""
+import numpy as np
+import pytest
+
+from oracle import hmc
+from paper_2010_02994_amd import workloads as W
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), device="cuda:0")
+
+
+def _run(w, p0, eps, steps, prec, bound, b0, b1):
+    import torch
+    from paper_2010_02994_amd import api
+    x, p, t = _dev(w.x), _dev(p0), _dev(w.t)
+    kind = {hmc.NONE: None, hmc.BOX: "box", hmc.DISC: "disc"}[bound]
+    g, out8 = api.leapfrog(x, p, t, w.params, eps, steps, prec=prec, bound=kind,
+                           b0=_dev(b0) if b0 is not None else None, b1=_dev(b1) if b1 is not None else None)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), p.cpu().numpy(), g.cpu().numpy(), out8.cpu().numpy()
+
+
+def _case(kind, d=2):
+    if kind == "cells":
+        # 100 m grid cells around the observed points, as in the gridded workload
+        w = W.random_case(101, 1500, d, ties=2, scale=1.0, t_span=40.0)
+        obs = np.round(w.x / 0.1) * 0.1
+        return w, hmc.BOX, obs - 0.05, obs + 0.05
+    w = W.random_case(102, 1500, d, ties=2, scale=1.0, t_span=40.0)
+    rng = np.random.default_rng(102)
+    r = np.where(rng.uniform(size=w.n) < 0.3, 0.0, rng.uniform(0.02, 0.2, w.n))
+    ang = rng.standard_normal((w.n, d))
+    ang /= np.linalg.norm(ang, axis=1, keepdims=True)
+    centre = w.x - ang * (r * rng.uniform(0, 1, w.n))[:, None]
+    return w, hmc.DISC, centre, r
+
+
+@pytest.mark.parametrize("kind,d", [("cells", 2), ("discs", 2), ("discs", 3)])
+def test_leapfrog_fp64_matches_oracle(kind, d):
+    w, bound, b0, b1 = _case(kind, d)
+    rng = np.random.default_rng(103)
+    p0 = rng.standard_normal(w.x.shape)
+    eps, steps = 0.004, 20
+    say(f"case leapfrog fp64 {kind} d={d} n={w.n}")
+    x, p, g, out8 = _run(w, p0, eps, steps, "fp64", bound, b0, b1)
+    xr, pr, gr = hmc.leapfrog(w.x, p0, eps, steps, hmc.hawkes_grad_fn(w.t, w.params), bound, b0, b1)
+    moved = np.linalg.norm(xr - w.x)
+    flips = int(np.sum(np.sign(pr) != np.sign(p0)))
+    e_x = np.linalg.norm(x - xr) / moved
+    e_p = np.linalg.norm(p - pr) / np.linalg.norm(pr)
+    e_g = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    say(f"  err x {e_x:.2e} p {e_p:.2e} grad {e_g:.2e} (momentum sign changes {flips})")
+    assert out8[7] == 0
+    assert flips > 0
+    assert e_x <= 1e-9 and e_p <= 1e-9 and e_g <= 1e-9
+    if bound == hmc.BOX:
+        assert np.all(x >= b0) and np.all(x <= b1)
+    else:
+        assert np.all(np.linalg.norm(x - b0, axis=1) <= b1 * (1 + 1e-14) + 1e-300)
+
+
+def test_leapfrog_mixed_unbounded_matches_oracle():
+    w = W.random_case(104, 2000, 2, ties=2, t_span=40.0)
+    rng = np.random.default_rng(104)
+    p0 = rng.standard_normal(w.x.shape)
+    eps, steps = 0.01, 20
+    say("case leapfrog mixed unbounded")
+    x, p, g, out8 = _run(w, p0, eps, steps, "mixed", hmc.NONE, None, None)
+    xr, pr, gr = hmc.leapfrog(w.x, p0, eps, steps, hmc.hawkes_grad_fn(w.t, w.params))
+    e_x = np.linalg.norm(x - xr) / np.linalg.norm(xr - w.x)
+    e_dp = np.linalg.norm(p - pr) / np.linalg.norm(pr - p0)
+    say(f"  err displacement {e_x:.2e} momentum change {e_dp:.2e}")
+    assert out8[7] == 0 and e_x <= 1e-4 and e_dp <= 1e-4
+
+
+def test_leapfrog_chained_trajectories():
+    """Two 5-step trajectories, the second reusing the first's final gradient,
+    equal one 10-step trajectory (the two half kicks at the seam add up to the
+    interior kick)."""
+    import torch
+    from paper_2010_02994_amd import api
+    w, bound, b0, b1 = _case("cells")
+    rng = np.random.default_rng(105)
+    p0 = rng.standard_normal(w.x.shape)
+    say("case leapfrog chained")
+    xa, pa, ga, _ = _run(w, p0, 0.004, 10, "fp64", bound, b0, b1)
+    x, p, t = _dev(w.x), _dev(p0), _dev(w.t)
+    g, _ = api.leapfrog(x, p, t, w.params, 0.004, 5, prec="fp64", bound="box", b0=_dev(b0), b1=_dev(b1))
+    g, _ = api.leapfrog(x, p, t, w.params, 0.004, 5, prec="fp64", bound="box", b0=_dev(b0), b1=_dev(b1),
+                        grad_x=g, have_grad=True)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(x.cpu().numpy(), xa, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(p.cpu().numpy(), pa, rtol=1e-12, atol=1e-12)
+    assert np.array_equal(g.cpu().numpy(), ga) or np.allclose(g.cpu().numpy(), ga, rtol=1e-12)

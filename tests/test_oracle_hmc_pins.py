@@ -1,0 +1,121 @@
+"""Pins of the oracle's leapfrog trajectories and reflecting walls to closed
+forms and invariants (Sec. 3 leapfrog; Sec. 2.2 box and disc supports)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import hmc
+from paper_2010_02994_amd import workloads as W
+
+
+def test_leapfrog_harmonic_oscillator_closed_form():
+    """For U = k x^2 / 2 one leapfrog step is the linear map
+    [[1 - e^2 k/2, e], [-e k (1 - e^2 k/4), 1 - e^2 k/2]] on (x, p)."""
+    k, eps, steps = 2.3, 0.11, 17
+    x0 = np.array([[0.7, -0.2]])
+    p0 = np.array([[0.1, 0.9]])
+    x, p, _ = hmc.leapfrog(x0, p0, eps, steps, lambda xx: -k * xx)
+    a = 1 - eps * eps * k / 2
+    M = np.array([[a, eps], [-eps * k * (1 - eps * eps * k / 4), a]])
+    Mn = np.linalg.matrix_power(M, steps)
+    for q in range(2):
+        ref = Mn @ np.array([x0[0, q], p0[0, q]])
+        assert x[0, q] == pytest.approx(ref[0], rel=1e-12)
+        assert p[0, q] == pytest.approx(ref[1], rel=1e-12)
+
+
+@pytest.mark.parametrize("eps", [0.3, 2.7, 11.4])
+def test_box_flight_is_triangle_wave(eps):
+    """A free particle between walls at lo and hi: the unfolded offset folds
+    with period 2 (hi - lo); the momentum sign flips with each wall hit."""
+    rng = np.random.default_rng(5)
+    lo = rng.uniform(-1, 0, 50)
+    hi = lo + rng.uniform(0.2, 1.0, 50)
+    x = lo + rng.uniform(0, 1, 50) * (hi - lo)
+    p = rng.standard_normal(50)
+    xn, pn = hmc.fly_box(x, p, lo, hi, eps)
+    w = hi - lo
+    u = x - lo + eps * p
+    hits = np.floor(u / w)
+    m = np.mod(u, 2 * w)
+    ref = lo + np.where(m <= w, m, 2 * w - m)
+    np.testing.assert_allclose(xn, ref, rtol=0, atol=1e-12 * (1 + abs(eps)))
+    np.testing.assert_array_equal(pn, np.where(hits % 2 == 0, p, -p))
+    # zero-width interval pins the coordinate and keeps the momentum
+    xz, pz = hmc.fly_box(np.array([0.3]), np.array([2.0]), np.array([0.3]), np.array([0.3]), eps)
+    assert xz[0] == 0.3 and pz[0] == 2.0
+
+
+def test_disc_flight_radial_bounce():
+    """From the centre along a diameter the motion is a triangle wave of
+    amplitude r."""
+    r, v, T = 0.8, 1.3, 5.1
+    x, p = hmc.fly_ball(np.array([[0.0, 0.0]]), np.array([[v, 0.0]]), np.zeros((1, 2)), np.array([r]), T)
+    s = v * T + r   # unfolded distance from the left wall
+    m = s % (4 * r)
+    ref = (m if m <= 2 * r else 4 * r - m) - r
+    assert x[0, 0] == pytest.approx(ref, abs=1e-12)
+    assert abs(x[0, 1]) < 1e-15
+    hits = math.floor((v * T + r) / (2 * r))
+    assert p[0, 0] == pytest.approx(v if hits % 2 == 0 else -v, rel=1e-15)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_disc_flight_invariants(d):
+    """Specular billiards in a ball keep the speed and the angular momentum
+    about the centre, and stay inside."""
+    rng = np.random.default_rng(6 + d)
+    n = 40
+    c = rng.standard_normal((n, d))
+    r = rng.uniform(0.2, 1.0, n)
+    dirn = rng.standard_normal((n, d))
+    dirn /= np.linalg.norm(dirn, axis=1, keepdims=True)
+    x = c + dirn * (r * rng.uniform(0, 0.95, n))[:, None]
+    p = rng.standard_normal((n, d))
+    xn, pn = hmc.fly_ball(x, p, c, r, 3.0)
+    np.testing.assert_allclose(np.linalg.norm(pn, axis=1), np.linalg.norm(p, axis=1), rtol=1e-12)
+    assert np.all(np.linalg.norm(xn - c, axis=1) <= r * (1 + 1e-15))
+    y0, y1 = x - c, xn - c
+    for a in range(d):
+        for b in range(a + 1, d):
+            L0 = y0[:, a] * p[:, b] - y0[:, b] * p[:, a]
+            L1 = y1[:, a] * pn[:, b] - y1[:, b] * pn[:, a]
+            np.testing.assert_allclose(L1, L0, rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("bound", [hmc.NONE, hmc.BOX, hmc.DISC])
+def test_hawkes_leapfrog_is_reversible(bound):
+    """Running back with the momentum negated returns to the start."""
+    w = W.random_case(7, 50, 2, ties=1, t_span=4.0)
+    rng = np.random.default_rng(7)
+    p0 = rng.standard_normal(w.x.shape)
+    b0 = b1 = None
+    if bound == hmc.BOX:
+        b0, b1 = w.x - 0.05, w.x + 0.05
+    elif bound == hmc.DISC:
+        b0, b1 = w.x.copy(), np.full(w.n, 0.06)
+    g = hmc.hawkes_grad_fn(w.t, w.params)
+    x1, p1, _ = hmc.leapfrog(w.x, p0, 0.01, 12, g, bound, b0, b1)
+    x2, p2, _ = hmc.leapfrog(x1, -p1, 0.01, 12, g, bound, b0, b1)
+    np.testing.assert_allclose(x2, w.x, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(-p2, p0, rtol=0, atol=1e-9)
+
+
+def test_hawkes_leapfrog_energy_error_is_second_order():
+    """H = -ell + |p|^2 / 2 drifts by O(eps^2) over a fixed time."""
+    w = W.random_case(8, 40, 2, t_span=3.0)
+    rng = np.random.default_rng(8)
+    p0 = rng.standard_normal(w.x.shape)
+    g = hmc.hawkes_grad_fn(w.t, w.params)
+
+    def H(x, p):
+        return -oracle.loglik_grad(x, w.t, w.params)[1] + 0.5 * float(np.sum(p * p))
+
+    h0 = H(w.x, p0)
+    errs = []
+    for eps, steps in ((0.02, 10), (0.01, 20), (0.005, 40)):
+        x, p, _ = hmc.leapfrog(w.x, p0, eps, steps, g)
+        errs.append(abs(H(x, p) - h0))
+    assert 2.5 < errs[0] / errs[1] < 6.0 and 2.5 < errs[1] / errs[2] < 6.0
