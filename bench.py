@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests per precision in the serving run (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--hmc-only", action="store_true",
+                    help="run only the leapfrog measurement (for profiling its kernels on their own)")
     ap.add_argument("--hmc-trajectories", type=int, default=3,
                     help="timed 20-step device leapfrog trajectories on the gridded 10,000-event workload (0 skips)")
     ap.add_argument("--mwg-steps", type=int, default=3000,
@@ -104,6 +106,9 @@ def main():
     from paper_2010_02994_amd import _lib, api, workloads
 
     dev = torch.device("cuda:0")
+    if args.hmc_only:
+        print(json.dumps({"hmc": leapfrog_bench(dev, max(1, args.hmc_trajectories))}), flush=True)
+        return
     w = workloads.config2(n=args.n)
     n, d = w.n, w.d
     x = torch.tensor(w.x, device=dev)
