@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests per precision in the serving run (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--bmds-reps", type=int, default=10,
+                    help="timed Bayesian MDS evaluations per case and precision (0 skips)")
     ap.add_argument("--hmc-only", action="store_true",
                     help="run only the leapfrog measurement (for profiling its kernels on their own)")
     ap.add_argument("--hmc-trajectories", type=int, default=3,
@@ -182,6 +184,7 @@ def main():
 
     mwg = mwg_bench(w, dev, args.mwg_steps) if args.mwg_steps > 0 else None
     hmc = leapfrog_bench(dev, args.hmc_trajectories) if args.hmc_trajectories > 0 else None
+    bmds = bmds_bench(dev, args.bmds_reps) if args.bmds_reps > 0 else None
 
     serve = None
     if args.serve_requests > 0:
@@ -206,6 +209,7 @@ def main():
            "speedup_mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
            "mwg": mwg,
            "hmc": hmc,
+           "bmds": bmds,
            "serve": serve,
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
@@ -299,6 +303,48 @@ def leapfrog_bench(dev, trajectories: int):
         out[prec] = {"ms_per_trajectory": el * 1e3, "ms_per_step": el * 1e3 / steps,
                      "pair_interactions_per_s": steps * w.n * (w.n - 1) / el,
                      "status": float(out8[7].item()), "inside_cells": inside}
+    return out
+
+
+def bmds_bench(dev, reps: int):
+    """Bayesian MDS log-likelihood + gradients: the influenza-like case
+    (N = 4,733 cases in D = 6, 64 countries, dissimilarities between country
+    centres, same-country pairs unobserved) and a larger N = 20,000, D = 6 case
+    whose dissimilarities are generated on the device (|z_n - z_n'| plus folded
+    normal noise).  The pass reads the strict lower triangle of the float64
+    matrix once, so its roofline is HBM: 4 N (N - 1) bytes per evaluation."""
+    import torch
+    from paper_2010_02994_amd import api, workloads
+    out = {}
+    c = workloads.bmds_case(4733, 4733, 6, groups=64)
+    cases = [("flu_n4733_d6_64countries", torch.tensor(c.x, device=dev), torch.tensor(c.delta, device=dev), c.sigma)]
+    del c
+    g = torch.Generator(device=dev)
+    g.manual_seed(20000)
+    n = 20000
+    z = torch.randn((n, 6), generator=g, device=dev, dtype=torch.float64)
+    dl = torch.cdist(z, z)
+    noise = torch.randn((n, n), generator=g, device=dev, dtype=torch.float64).tril_(-1)
+    dl.add_(0.3 * (noise + noise.T)).abs_()
+    del noise
+    x = z + 0.1 * torch.randn((n, 6), generator=g, device=dev, dtype=torch.float64)
+    cases.append(("dense_n20000_d6", x, dl, 0.3))
+    for name, x, dl, sigma in cases:
+        n = x.shape[0]
+        rec = {"n": n, "d": int(x.shape[1]), "delta_bytes_read": 4 * n * (n - 1)}
+        for prec in ("mixed", "fp64"):
+            o, gx = api.bmds(x, dl, sigma, prec=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                o, gx = api.bmds(x, dl, sigma, prec=prec, grad_x=gx, out4=o)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / reps
+            rec[prec] = {"ms": el * 1e3, "pair_interactions_per_s": n * (n - 1) / el,
+                         "delta_GB_per_s": 4 * n * (n - 1) / el / 1e9,
+                         "hbm_frac": 4 * n * (n - 1) / el / 8e12, "status": float(o[3].item())}
+        out[name] = rec
+        del x, dl
     return out
 
 

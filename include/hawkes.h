@@ -200,6 +200,31 @@ int hawkes_leapfrog(double* x /* device, n*d */, double* p /* device, n*d */, co
                     double* out8 /* device, 8 */);
 
 /* ------------------------------------------------------------------------
+ * Bayesian multidimensional scaling (Sec. 2.2.3, eq. bmdsLikelihood): the
+ * second pairwise term of the influenza model's posterior.  Observed
+ * dissimilarities delta_{nn'} (n > n') are independent normals with mean
+ * d_{nn'} = |x_n - x_n'| and variance sigma^2, truncated to positive values:
+ *   ell = -(M/2) log sigma^2 - sum_{n>n'} [ (delta - d)^2/(2 sigma^2) + log Phi(d/sigma) ]
+ * (the paper's density up to its constant), M = number of observed pairs.
+ */
+
+/* Device workspace of hawkes_bmds (0 if n or d is invalid; n <= 2^20). */
+size_t hawkes_bmds_workspace_bytes(int64_t n, int d);
+
+/* ell, d ell/d sigma and (unless grad_x is NULL) d ell/d x for the latent
+ * locations x (device, n x d row-major float64) and the dissimilarities delta
+ * (device, n x n row-major float64; only the strict lower triangle
+ * delta[i*n + j], j < i, is read; NaN marks an unobserved pair, a negative or
+ * infinite entry is a data error).  prec: HAWKES_FP64, or HAWKES_MIXED (float32
+ * pair arithmetic, float64 sums).  out4 (device) receives [ell, d ell/d sigma,
+ * M, status]; on a data error ell and d ell/d sigma are NaN, status is
+ * HAWKES_EDATA and grad_x is NaN.  A coincident pair (d = 0) adds no direction
+ * to the gradient.  Enqueue only; host-side argument errors return at once
+ * (sigma must be finite and > 0: HAWKES_EPARAM). */
+int hawkes_bmds(const double* x, const double* delta, int64_t n, int d, double sigma, int prec, void* ws,
+                size_t ws_bytes, void* stream, double* out4 /* device, 4 */, double* grad_x /* device or NULL */);
+
+/* ------------------------------------------------------------------------
  * Serving: continuous batching of evaluation requests from many HMC chains
  * (one request = one log-likelihood + gradient at new latent locations).
  *

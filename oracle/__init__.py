@@ -46,7 +46,9 @@ def _lib(threads: bool):
         lib.oracle_rates.argtypes = [d, d, i64, ctypes.c_int, d, d, d]
         lib.oracle_grad_rows.argtypes = [d, d, i64, ctypes.c_int, d, d, ctypes.POINTER(i64), i64, d]
         lib.oracle_diagnostics.argtypes = [d, d, i64, ctypes.c_int, d, ctypes.c_double, d, ctypes.POINTER(i64)]
-        for f in (lib.oracle_loglik_grad, lib.oracle_rates, lib.oracle_grad_rows, lib.oracle_diagnostics):
+        lib.oracle_bmds.argtypes = [d, d, i64, ctypes.c_int, ctypes.c_double, d, d]
+        for f in (lib.oracle_loglik_grad, lib.oracle_rates, lib.oracle_grad_rows, lib.oracle_diagnostics,
+                  lib.oracle_bmds):
             f.restype = ctypes.c_int
         _libs[key] = lib
     return _libs[key]
@@ -158,3 +160,19 @@ def loglik_reweight(x, t, params_new, threads: bool = True):
     """(ell, d ell/d mu, d ell/d theta) at the given parameters."""
     st, ll, _, gp = loglik_grad(x, t, params_new, threads=threads, want_grad_x=False)
     return st, ll, float(gp[0]), float(gp[3])
+
+
+def bmds(x, delta, sigma, threads: bool = True, want_grad_x: bool = True):
+    """Bayesian MDS log-likelihood (Sec. 2.2.3): returns (status, ell,
+    d ell/d sigma, pair count M, grad_x (N, D) or None).  delta is N x N; only
+    the strict lower triangle is read, NaN marks an unobserved pair."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    delta = np.ascontiguousarray(delta, dtype=np.float64)
+    n, d = x.shape
+    assert delta.shape == (n, n)
+    out = np.zeros(3)
+    gx = np.zeros((n, d)) if want_grad_x else None
+    st = _lib(threads).oracle_bmds(_p(x), _p(delta), n, d, float(sigma), _p(out), _p(gx))
+    return st, float(out[0]), float(out[1]), float(out[2]), gx

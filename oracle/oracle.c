@@ -276,3 +276,79 @@ int oracle_diagnostics(const double* x, const double* t, int64_t n, int d, const
   *rows_below = cnt;
   return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Bayesian multidimensional scaling (Sec. 2.2.3, eq. "bmdsLikelihood"):
+ * observed dissimilarities delta_{nn'} (n > n') are independent normals with
+ * mean d_{nn'} = |x_n - x_n'| and variance sigma^2, truncated to delta > 0:
+ *   ell = -(M/2) log sigma^2 - sum_{n>n'} [ (delta - d)^2 / (2 sigma^2) + log Phi(d / sigma) ]
+ * with M the number of pairs (the paper's exponent N(1-N)/4 of sigma^2 is -M/2
+ * when every pair is observed).  A NaN delta marks a pair with no observation:
+ * it contributes nothing and is not counted in M.
+ * Derivatives, differentiating the summand term by term (z = d / sigma,
+ * rho = phi(z) / Phi(z)):
+ *   d ell/d x_n   = sum_{n' != n} [ (delta - d)/sigma^2 - rho/sigma ] (x_n - x_n') / d
+ *   d ell/d sigma = -M/sigma + sum [ (delta - d)^2 / sigma^3 + rho z / sigma ]
+ * A coincident pair (d = 0) contributes no direction to d ell/d x.
+ * out3 = (ell, d ell/d sigma, M).  Status: EINVAL for a negative or infinite
+ * delta, non-finite x or sigma <= 0. */
+static void bmds_pair(const double* xi, const double* xj, int d, double delta, double sigma, double* term,
+                      double* dsig, double* coef, double* dist) {
+  double r2 = 0.0;
+  for (int k = 0; k < d; ++k) { double v = xi[k] - xj[k]; r2 += v * v; }
+  const double dd = sqrt(r2);
+  const double z = dd / sigma;
+  const double Phi = std_normal_cdf(z);
+  const double rho = std_normal_pdf(z) / Phi;
+  const double res = delta - dd;
+  *term = -res * res / (2.0 * sigma * sigma) - log(Phi);
+  *dsig = res * res / (sigma * sigma * sigma) + rho * z / sigma;
+  *coef = dd > 0.0 ? (res / (sigma * sigma) - rho / sigma) / dd : 0.0;
+  *dist = dd;
+}
+
+int oracle_bmds(const double* x, const double* delta, int64_t n, int d, double sigma, double* out3,
+                double* grad_x) {
+  if (n < 1 || d < 1 || d > 64 || !x || !delta || !out3) return ORACLE_EINVAL;
+  if (!(sigma > 0.0) || !isfinite(sigma)) return ORACLE_EINVAL;
+  for (int64_t i = 0; i < n * d; ++i) if (!isfinite(x[i])) return ORACLE_EINVAL;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < i; ++j) {
+      const double v = delta[i * n + j];
+      if (!isnan(v) && (v < 0.0 || isinf(v))) return ORACLE_EINVAL;
+    }
+  ksum sl, sd, sm;
+  memset(&sl, 0, sizeof(sl)); memset(&sd, 0, sizeof(sd)); memset(&sm, 0, sizeof(sm));
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < i; ++j) {
+      const double v = delta[i * n + j];
+      if (isnan(v)) continue;
+      double term, dsig, coef, dist;
+      bmds_pair(x + i * d, x + j * d, d, v, sigma, &term, &dsig, &coef, &dist);
+      ks_add(&sl, term);
+      ks_add(&sd, dsig);
+      ks_add(&sm, 1.0);
+    }
+  const double M = ks_val(&sm);
+  out3[0] = -0.5 * M * log(sigma * sigma) + ks_val(&sl);
+  out3[1] = -M / sigma + ks_val(&sd);
+  out3[2] = M;
+  if (grad_x) {
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (i = 0; i < n; ++i) {
+      ksum g[64];
+      memset(g, 0, sizeof(ksum) * d);
+      for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const double v = i > j ? delta[i * n + j] : delta[j * n + i];
+        if (isnan(v)) continue;
+        double term, dsig, coef, dist;
+        bmds_pair(x + i * d, x + j * d, d, v, sigma, &term, &dsig, &coef, &dist);
+        for (int k = 0; k < d; ++k) ks_add(&g[k], coef * (x[i * d + k] - x[j * d + k]));
+      }
+      for (int k = 0; k < d; ++k) grad_x[i * d + k] = ks_val(&g[k]);
+    }
+  }
+  return ORACLE_OK;
+}

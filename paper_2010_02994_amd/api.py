@@ -233,3 +233,38 @@ def leapfrog(x: torch.Tensor, p: torch.Tensor, t: torch.Tensor, params, eps: flo
     if st != _lib.OK:
         raise HawkesError(st, "hawkes_leapfrog")
     return grad_x, out8
+
+
+_bmds_ws: dict = {}
+
+
+def bmds(x: torch.Tensor, delta: torch.Tensor, sigma: float, prec="fp64", grad_x: torch.Tensor | None = None,
+         want_grad: bool = True, out4: torch.Tensor | None = None):
+    """Enqueue the Bayesian MDS log-likelihood on the current stream.  x: (N, D)
+    float64 device; delta: (N, N) float64 device (strict lower triangle read,
+    NaN = unobserved).  Returns (out4 = [loglik, d/d sigma, pairs, status],
+    grad_x or None)."""
+    if x.dtype != torch.float64 or delta.dtype != torch.float64:
+        raise ValueError("x and delta must be float64")
+    x, delta = x.contiguous(), delta.contiguous()
+    n, d = x.shape
+    if delta.shape != (n, n):
+        raise ValueError("delta must be (N, N)")
+    need = int(_lib.lib().hawkes_bmds_workspace_bytes(n, d))
+    if need == 0:
+        raise HawkesError(_lib.EINVAL, "bmds workspace size")
+    key = (x.device, _stream_ptr(x.device))
+    ws = _bmds_ws.get(key)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+        _bmds_ws[key] = ws
+    if want_grad and grad_x is None:
+        grad_x = torch.empty_like(x)
+    if out4 is None:
+        out4 = torch.empty(4, dtype=torch.float64, device=x.device)
+    st = _lib.lib().hawkes_bmds(x.data_ptr(), delta.data_ptr(), n, d, float(sigma), _prec(prec), ws.data_ptr(),
+                                ws.numel(), _stream_ptr(x.device), out4.data_ptr(),
+                                grad_x.data_ptr() if want_grad else None)
+    if st != _lib.OK:
+        raise HawkesError(st, "hawkes_bmds")
+    return out4, (grad_x if want_grad else None)

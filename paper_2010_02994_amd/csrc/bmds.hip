@@ -1,0 +1,376 @@
+// libhawkes: Bayesian multidimensional scaling log-likelihood and its
+// gradients (arXiv 2010.02994, Sec. 2.2.3, eq. bmdsLikelihood), the second
+// pairwise term of the influenza model's posterior.
+//
+// For observed dissimilarities delta_{nn'} (n > n'), d_{nn'} = |x_n - x_n'|:
+//   ell = -(M/2) log sigma^2 - sum_{n>n'} [ (delta - d)^2 / (2 sigma^2) + log Phi(d / sigma) ]
+//   d ell/d x_n   = sum_{n'} [ (delta - d)/sigma^2 - rho/sigma ] (x_n - x_n') / d,  rho = phi(z)/Phi(z), z = d/sigma
+//   d ell/d sigma = -M/sigma + sum [ (delta - d)^2/sigma^3 + rho z / sigma ]
+// M counts the observed pairs (a NaN delta is unobserved).  The pass streams
+// the strict lower triangle of the N x N matrix once: it is bound by HBM when
+// the pair arithmetic is float32 and close to balanced in float64.
+//
+// Tiles: row band I (rows [64 I, 64 I + 64)) meets column chunks
+// J = 0 .. floor(I / 4) of 256 columns.  A workgroup of 256 lanes takes one
+// tile, one column per lane, and walks the 64 rows: the lanes of a row read
+// consecutive delta entries (one coalesced 2 KB row segment per step).  Column
+// sums stay in each lane; the row sums are wave totals formed with DPP row
+// shifts and row broadcasts (no LDS traffic), then added over the four waves
+// in a fixed order.  Per-tile partials are reduced per event in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+#include "../../include/hawkes.h"
+#include "hawkes_common.hpp"
+
+namespace hawkes {
+namespace bmds {
+
+constexpr int kTR = 64;        // rows per tile
+constexpr int kTC = 256;       // columns per tile (one per lane of the workgroup)
+constexpr int kThreads = 256;
+constexpr int kFinalThreads = 1024;
+constexpr int kPrefetch = 8;   // rows whose entries are loaded ahead of their arithmetic
+
+// First tile of row band I: sum over I' < I of (floor(I'/4) + 1).
+__host__ __device__ inline int64_t band_offset(int64_t I) {
+  const int64_t q = I / 4, r = I % 4;
+  return I + 2 * q * (q - 1) + r * q;
+}
+
+struct Args {
+  const double* x;
+  const double* delta;
+  int n, nb;
+  int64_t ntiles;
+  double sigma, inv_sigma, inv_s2;
+  double* prow;   // ntiles x kTR x D
+  double* pcol;   // ntiles x kTC x D
+  double* ptile;  // ntiles x 4: sum of summands, sum of sigma terms, pairs, invalid deltas
+  double* out4;   // [ell, d ell/d sigma, pairs, status]
+  double* grad_x; // n x D or null
+};
+
+// Wave totals in lane 63: inclusive row scans by DPP row_shr 1, 2, 4, 8, then
+// row_bcast:15 into rows 1 and 3 and row_bcast:31 into rows 2 and 3; lanes
+// without a source read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, true));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), CTRL, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWS, 0xf, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL, int ROWS, typename R>
+__device__ __forceinline__ R dpp_step(R v) {
+  if constexpr (std::is_same<R, float>::value) return dpp_f<CTRL, ROWS>(v);
+  else return dpp_d<CTRL, ROWS>(v);
+}
+// K independent totals, step by step across the K values so that no DPP read
+// waits on the add just before it.
+template <int K, typename R>
+__device__ __forceinline__ void wave_totals_lane63(R* v) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x111, 0xf>(v[k]);  // row_shr:1
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x112, 0xf>(v[k]);  // row_shr:2
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x114, 0xf>(v[k]);  // row_shr:4
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x118, 0xf>(v[k]);  // row_shr:8
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x142, 0xa>(v[k]);  // row_bcast:15
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x143, 0xc>(v[k]);  // row_bcast:31
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// erfc(w) for w >= 0 in float32: the Chebyshev-fitted form
+// t exp(-w^2 + P(t)), t = 1/(1 + w/2), of Press et al., Numerical Recipes
+// (2nd ed., Sec. 6.2, "erfcc"), relative error below 1.2e-7 for all w >= 0,
+// built on the hardware reciprocal and base-2 exponential.
+__device__ __forceinline__ float erfc_cheb(float w) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, w, 1.0f));
+  float p = 0.17087277f;
+  p = fmaf(p, t, -0.82215223f);
+  p = fmaf(p, t, 1.48851587f);
+  p = fmaf(p, t, -1.13520398f);
+  p = fmaf(p, t, 0.27886807f);
+  p = fmaf(p, t, -0.18628806f);
+  p = fmaf(p, t, 0.09678418f);
+  p = fmaf(p, t, 0.37409196f);
+  p = fmaf(p, t, 1.00002368f);
+  p = fmaf(p, t, -1.26551223f);
+  return t * __builtin_amdgcn_exp2f((p - w * w) * 1.44269504088896341f);
+}
+
+// Summand, sigma term and gradient coefficient of one observed pair.  The
+// upper tail q = 1 - Phi(z) is formed directly, so log Phi keeps small tails.
+template <typename R>
+__device__ __forceinline__ void pair_terms(R dist, R delta, R inv_sigma, R inv_s2, R& term, R& dsig, R& coef) {
+  const R z = dist * inv_sigma;
+  const R res = delta - dist;
+  if constexpr (std::is_same<R, float>::value) {
+    const float q = 0.5f * erfc_cheb(z * 0.70710678118654752f);
+    const float phi = 1.0f - q;
+    const float lphi = __builtin_amdgcn_logf(phi) * 0.69314718055994531f;
+    const float pdf = 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z);
+    const float rho = pdf * __builtin_amdgcn_rcpf(phi);
+    term = -0.5f * res * res * inv_s2 - lphi;
+    dsig = (res * res * inv_s2 + rho * z) * inv_sigma;
+    coef = dist > 0.0f ? (res * inv_s2 - rho * inv_sigma) * __builtin_amdgcn_rcpf(dist) : 0.0f;
+  } else {
+    const double q = 0.5 * erfc(z * 0.70710678118654752440);
+    const double lphi = log1p(-q);
+    const double pdf = 0.39894228040143267794 * exp(-0.5 * z * z);
+    const double rho = pdf / (1.0 - q);
+    term = -0.5 * res * res * inv_s2 - lphi;
+    dsig = (res * res * inv_s2 + rho * z) * inv_sigma;
+    coef = dist > 0.0 ? (res * inv_s2 - rho * inv_sigma) / dist : 0.0;
+  }
+}
+
+template <int D, bool MIX>
+__global__ void __launch_bounds__(kThreads) k_bmds_tiles(Args a) {
+  using R = typename std::conditional<MIX, float, double>::type;
+  __shared__ R s_x[kTR][D];
+  __shared__ R s_row[kThreads / 64][kTR][D];
+  __shared__ double sh[kThreads];
+  const int64_t tile = blockIdx.x;
+  int lo = 0, hi = a.nb - 1;   // band: largest I with band_offset(I) <= tile
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (band_offset(mid) <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const int I = lo;
+  const int J = (int)(tile - band_offset(I));
+  const int i0 = I * kTR;
+  const int j = J * kTC + threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < kTR * D; e += kThreads) {
+    const int r = e / D, q = e % D;
+    const int i = i0 + r;
+    s_x[r][q] = i < a.n ? (R)a.x[(int64_t)i * D + q] : R(0);
+  }
+  R xj[D], g[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    xj[q] = j < a.n ? (R)a.x[(int64_t)j * D + q] : R(0);
+    g[q] = R(0);
+  }
+  const R inv_sigma = (R)a.inv_sigma, inv_s2 = (R)a.inv_s2;
+  R tsum = R(0), dsum = R(0);
+  int cnt = 0, bad = 0;
+  __syncthreads();
+  const int rows = min(kTR, a.n - i0);
+  for (int r0 = 0; r0 < rows; r0 += kPrefetch) {
+    // the next rows' entries first, so kPrefetch loads are in flight at once
+    double v[kPrefetch];
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+      const int i = i0 + r0 + u;
+      v[u] = (r0 + u < rows && j < i) ? a.delta[(int64_t)i * a.n + j] : (double)NAN;
+    }
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+      const int r = r0 + u;
+      if (r >= rows) break;
+      R gi[D];
+#pragma unroll
+      for (int q = 0; q < D; ++q) gi[q] = R(0);
+      if (!isnan(v[u])) {
+        if (v[u] < 0.0 || isinf(v[u])) {
+          bad += 1;
+        } else {
+          R diff[D], r2 = R(0);
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            diff[q] = s_x[r][q] - xj[q];
+            r2 += diff[q] * diff[q];
+          }
+          R term, dsig, coef;
+          R dist;
+          if constexpr (MIX) dist = __builtin_amdgcn_sqrtf(r2);
+          else dist = sqrt(r2);
+          pair_terms<R>(dist, (R)v[u], inv_sigma, inv_s2, term, dsig, coef);
+          tsum += term;
+          dsum += dsig;
+          cnt += 1;
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            gi[q] = coef * diff[q];
+            g[q] -= gi[q];
+          }
+        }
+      }
+      wave_totals_lane63<D, R>(gi);
+      if (lane == 63)
+#pragma unroll
+        for (int q = 0; q < D; ++q) s_row[w][r][q] = gi[q];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < rows * D; e += kThreads) {
+    const int r = e / D, q = e % D;
+    double s = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < kThreads / 64; ++ww) s += (double)s_row[ww][r][q];
+    a.prow[(tile * kTR + r) * D + q] = s;
+  }
+#pragma unroll
+  for (int q = 0; q < D; ++q) a.pcol[(tile * kTC + threadIdx.x) * D + q] = (double)g[q];
+  const double t0 = block_sum((double)tsum, sh);
+  const double t1 = block_sum((double)dsum, sh);
+  const double t2 = block_sum((double)cnt, sh);
+  const double t3 = block_sum((double)bad, sh);
+  if (threadIdx.x == 0) {
+    a.ptile[tile * 4 + 0] = t0;
+    a.ptile[tile * 4 + 1] = t1;
+    a.ptile[tile * 4 + 2] = t2;
+    a.ptile[tile * 4 + 3] = t3;
+  }
+}
+
+// One workgroup: the tile totals in tile order, the -M/2 log sigma^2 and
+// -M/sigma terms, and the data checks (invalid deltas, non-finite x).
+__global__ void __launch_bounds__(kFinalThreads) k_bmds_final(Args a, int D) {
+  __shared__ double sh[kFinalThreads];
+  double v[4] = {0, 0, 0, 0};
+  for (int64_t t = threadIdx.x; t < a.ntiles; t += kFinalThreads)
+    for (int k = 0; k < 4; ++k) v[k] += a.ptile[t * 4 + k];
+  double nonfinite = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)a.n * D; e += kFinalThreads)
+    if (!isfinite(a.x[e])) nonfinite += 1.0;
+  for (int k = 0; k < 4; ++k) v[k] = block_sum(v[k], sh);
+  nonfinite = block_sum(nonfinite, sh);
+  if (threadIdx.x == 0) {
+    const double M = v[2];
+    const bool bad = v[3] > 0.0 || nonfinite > 0.0;
+    a.out4[0] = bad ? NAN : -0.5 * M * log(a.sigma * a.sigma) + v[0];
+    a.out4[1] = bad ? NAN : -M * a.inv_sigma + v[1];
+    a.out4[2] = M;
+    a.out4[3] = bad ? (double)HAWKES_EDATA : 0.0;
+  }
+}
+
+// Per event: its row partials over the chunks of its band, then its column
+// partials over the bands that reach its chunk (fixed order).
+template <int D>
+__global__ void __launch_bounds__(256) k_bmds_reduce(Args a) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= a.n) return;
+  double g[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) g[q] = 0.0;
+  if (a.out4[3] != 0.0) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) a.grad_x[(int64_t)n * D + q] = NAN;
+    return;
+  }
+  const int I = n / kTR, r = n % kTR;
+  const int64_t o = band_offset(I);
+  for (int J = 0; J <= I / 4; ++J)
+#pragma unroll
+    for (int q = 0; q < D; ++q) g[q] += a.prow[((o + J) * kTR + r) * D + q];
+  const int J = n / kTC, c = n % kTC;
+  for (int Ib = 4 * J; Ib < a.nb; ++Ib)
+#pragma unroll
+    for (int q = 0; q < D; ++q) g[q] += a.pcol[((band_offset(Ib) + J) * kTC + c) * D + q];
+#pragma unroll
+  for (int q = 0; q < D; ++q) a.grad_x[(int64_t)n * D + q] = g[q];
+}
+
+struct Pieces {
+  size_t prow, pcol, ptile, total;
+};
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+static Pieces pieces(int64_t n, int d, int64_t& ntiles, int& nb) {
+  nb = (int)((n + kTR - 1) / kTR);
+  ntiles = band_offset(nb);
+  Pieces p;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+  p.prow = take(sizeof(double) * (size_t)ntiles * kTR * d);
+  p.pcol = take(sizeof(double) * (size_t)ntiles * kTC * d);
+  p.ptile = take(sizeof(double) * (size_t)ntiles * 4);
+  p.total = o;
+  return p;
+}
+
+template <int D>
+static void launch(const Args& a, int prec, hipStream_t s) {
+  if (prec == HAWKES_MIXED) k_bmds_tiles<D, true><<<(unsigned)a.ntiles, kThreads, 0, s>>>(a);
+  else k_bmds_tiles<D, false><<<(unsigned)a.ntiles, kThreads, 0, s>>>(a);
+  k_bmds_final<<<1, kFinalThreads, 0, s>>>(a, D);
+  if (a.grad_x) k_bmds_reduce<D><<<(a.n + 255) / 256, 256, 0, s>>>(a);
+}
+
+}  // namespace bmds
+}  // namespace hawkes
+
+extern "C" {
+
+size_t hawkes_bmds_workspace_bytes(int64_t n, int d) {
+  if (n < 2 || n > (int64_t(1) << 20) || d < 1 || d > hawkes::kMaxD) return 0;
+  int64_t ntiles;
+  int nb;
+  return hawkes::bmds::pieces(n, d, ntiles, nb).total;
+}
+
+int hawkes_bmds(const double* x, const double* delta, int64_t n, int d, double sigma, int prec, void* ws,
+                size_t ws_bytes, void* stream, double* out4, double* grad_x) {
+  using namespace hawkes::bmds;
+  if (!x || !delta || !ws || !out4) return HAWKES_EINVAL;
+  if (prec != HAWKES_FP64 && prec != HAWKES_MIXED) return HAWKES_EINVAL;
+  const size_t need = hawkes_bmds_workspace_bytes(n, d);
+  if (need == 0 || ws_bytes < need) return HAWKES_EINVAL;
+  if (!std::isfinite(sigma) || !(sigma > 0.0)) return HAWKES_EPARAM;
+  Args a;
+  const Pieces pc = pieces(n, d, a.ntiles, a.nb);
+  char* w = static_cast<char*>(ws);
+  a.x = x;
+  a.delta = delta;
+  a.n = (int)n;
+  a.sigma = sigma;
+  a.inv_sigma = 1.0 / sigma;
+  a.inv_s2 = 1.0 / (sigma * sigma);
+  a.prow = reinterpret_cast<double*>(w + pc.prow);
+  a.pcol = reinterpret_cast<double*>(w + pc.pcol);
+  a.ptile = reinterpret_cast<double*>(w + pc.ptile);
+  a.out4 = out4;
+  a.grad_x = grad_x;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  (void)hipGetLastError();
+  switch (d) {
+    case 1: launch<1>(a, prec, s); break;
+    case 2: launch<2>(a, prec, s); break;
+    case 3: launch<3>(a, prec, s); break;
+    case 4: launch<4>(a, prec, s); break;
+    case 5: launch<5>(a, prec, s); break;
+    case 6: launch<6>(a, prec, s); break;
+    case 7: launch<7>(a, prec, s); break;
+    case 8: launch<8>(a, prec, s); break;
+  }
+  return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+}
+
+}  // extern "C"

@@ -203,3 +203,46 @@ def random_case(seed: int, n: int, d: int, ties: int = 0, scale: float = 1.0,
                            rng.uniform(0.1, 0.8), rng.uniform(0.3, 2.0), rng.uniform(0.2, 1.0)])
     return Workload(f"rand_s{seed}_n{n}_d{d}", np.ascontiguousarray(x), np.ascontiguousarray(t),
                     np.asarray(params, dtype=np.float64), seed=seed)
+
+
+@dataclasses.dataclass
+class BmdsCase:
+    name: str
+    x: np.ndarray        # (N, D) latent locations (the state a sampler moves)
+    delta: np.ndarray    # (N, N) observed dissimilarities, symmetric, NaN where unobserved
+    sigma: float
+    seed: int
+
+
+def bmds_case(seed: int, n: int, d: int, missing: float = 0.0, sigma: float = 0.3,
+              groups: int = 0) -> BmdsCase:
+    """Seeded dissimilarity data in the shape of the influenza application
+    (Sec. 2.2.3): true positions z, observed delta = |z_n - z_n'| plus normal
+    noise of sd sigma, folded to be positive; the latent x starts at z plus a
+    perturbation.  With `groups` > 0 every event belongs to one of that many
+    countries and delta is the distance between the country centres (the
+    air-traffic matrix is country by country), with same-country pairs
+    unobserved.  `missing` marks a further random fraction unobserved."""
+    rng = np.random.default_rng(seed)
+    if groups > 0:
+        centres = 2.0 * rng.standard_normal((groups, d))
+        g = rng.integers(0, groups, size=n)
+        z = centres[g] + 0.05 * rng.standard_normal((n, d))
+        base = np.linalg.norm(centres[g][:, None, :] - centres[g][None, :, :], axis=-1)
+    else:
+        z = rng.standard_normal((n, d))
+        base = np.linalg.norm(z[:, None, :] - z[None, :, :], axis=-1)
+    noise = sigma * rng.standard_normal((n, n))
+    noise = np.tril(noise, -1)
+    noise = noise + noise.T
+    delta = np.abs(base + noise)
+    if groups > 0:
+        delta[g[:, None] == g[None, :]] = np.nan
+    if missing > 0:
+        m = np.tril(rng.uniform(size=(n, n)) < missing, -1)
+        m = m | m.T
+        delta[m] = np.nan
+    np.fill_diagonal(delta, np.nan)
+    x = z + 0.1 * rng.standard_normal((n, d))
+    return BmdsCase(f"bmds_s{seed}_n{n}_d{d}", np.ascontiguousarray(x), np.ascontiguousarray(delta), float(sigma),
+                    seed)

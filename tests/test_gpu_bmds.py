@@ -1,0 +1,61 @@
+"""GPU parity of the Bayesian MDS log-likelihood and gradients against the
+CPU oracle (Sec. 2.2.3)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_02994_amd import workloads as W
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": {"ll": 1e-12, "ds": 1e-11, "gx": 1e-11}, "mixed": {"ll": 1e-5, "ds": 1e-4, "gx": 1e-4}}
+
+
+def _gpu(c, prec):
+    import torch
+    from paper_2010_02994_amd import api
+    x = torch.tensor(c.x, device="cuda:0")
+    dl = torch.tensor(c.delta, device="cuda:0")
+    out4, gx = api.bmds(x, dl, c.sigma, prec=prec)
+    torch.cuda.synchronize()
+    return out4.cpu().numpy(), gx.cpu().numpy()
+
+
+def _check(c, prec, label):
+    st, ll, ds, M, gx_ref = oracle.bmds(c.x, c.delta, c.sigma)
+    assert st == 0
+    o, gx = _gpu(c, prec)
+    e_ll = abs(o[0] - ll) / abs(ll)
+    e_ds = abs(o[1] - ds) / max(abs(ds), M / c.sigma)
+    e_gx = np.linalg.norm(gx - gx_ref) / np.linalg.norm(gx_ref)
+    say(f"  bmds {label} {prec}: ll {o[0]:.15g} ref {ll:.15g} | err ll {e_ll:.2e} dsigma {e_ds:.2e} gx {e_gx:.2e}")
+    t = TOL[prec]
+    assert o[3] == 0 and o[2] == M
+    assert e_ll <= t["ll"] and e_ds <= t["ds"] and e_gx <= t["gx"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("seed,n,d,missing,groups", [(1, 1000, 2, 0.1, 0), (2, 700, 6, 0.0, 40), (3, 2, 3, 0.0, 0),
+                                                      (4, 65, 2, 0.0, 0), (5, 257, 4, 0.5, 0), (6, 1500, 8, 0.0, 0)])
+def test_bmds_matches_oracle(prec, seed, n, d, missing, groups):
+    c = W.bmds_case(seed, n, d, missing=missing, groups=groups)
+    say(f"case bmds n={n} d={d} missing={missing} groups={groups} prec={prec}")
+    _check(c, prec, c.name)
+
+
+def test_bmds_invalid_delta_is_reported():
+    import torch
+    c = W.bmds_case(7, 300, 2)
+    c.delta[200, 17] = -1.0
+    say("case bmds invalid delta")
+    o, gx = _gpu(c, "fp64")
+    assert o[3] == -3 and np.isnan(o[0]) and np.all(np.isnan(gx))
+
+
+def test_bmds_deterministic():
+    c = W.bmds_case(8, 900, 3, missing=0.2)
+    say("case bmds determinism")
+    a = _gpu(c, "mixed")
+    b = _gpu(c, "mixed")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
