@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests per precision in the serving run (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--cull-steps", type=int, default=5,
+                    help="timed steps with exact culling, reported apart from the headline (0 skips)")
     ap.add_argument("--bmds-reps", type=int, default=10,
                     help="timed Bayesian MDS evaluations per case and precision (0 skips)")
     ap.add_argument("--hmc-only", action="store_true",
@@ -145,7 +147,7 @@ def main():
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         acc = np.zeros(12)
-        for _ in range(stage_steps):
+        for _ in range(stage_steps if "+cull" not in prec else 0):
             st = L.hawkes_grad_timed(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), pc, ws.data_ptr(),
                                      ws.numel(), stream, ctypes.byref(ll), gx.data_ptr(), gp, stage)
             assert st == 0, _lib.strerror(st)
@@ -162,6 +164,22 @@ def main():
         fp64 = {"value": pairs / sec64, "ms_per_step": sec64 * 1e3,
                 "stage_ms": {k: round(float(v), 4) for k, v in zip(STAGES, stage64)},
                 "loglik_rel_diff_mixed_vs_fp64": abs(ll_m - ll_64) / abs(ll_64)}
+
+    # exact culling (bitwise-identical results), reported apart from the all-pairs headline
+    culling = None
+    if args.cull_steps > 0:
+        gx_all = gx.clone()
+        culling = {"note": "column tiles whose pair terms all underflow are skipped; results bitwise equal"}
+        for base in ([args.prec] + (["fp64"] if args.prec == "mixed" and args.fp64_steps > 0 else [])):
+            sec_all = sec_mixed if base == args.prec else sec64
+            ref = gx.clone()
+            run(base, 1, 0, 0)
+            ref.copy_(gx)
+            ll_ref = ll_m if base == args.prec else ll_64
+            sec_c, _, ll_c = run(base + "+cull", args.cull_steps, 1, 0)
+            culling[base] = {"ms_per_step": sec_c * 1e3, "speedup_vs_all_pairs": sec_all / sec_c,
+                             "bitwise_equal": bool(ll_c == ll_ref and torch.equal(gx, ref))}
+        gx.copy_(gx_all)
 
     # dominant kernel and its roofline (algorithmic work per launch / measured duration)
     pass_ms = {k: float(stage_ms[STAGES.index(k)]) for k in ("pass1", "pass2")}
@@ -206,6 +224,7 @@ def main():
            "stage_ms_note": "stages timed in sequence on one stream (hawkes_grad_timed); ms_per_step is "
                             "hawkes_grad, where flaglist..final2 and fix2b/fix2a overlap pass2 on a side stream",
            "fp64": fp64,
+           "exact_culling": culling,
            "speedup_mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,
            "mwg": mwg,
            "hmc": hmc,

@@ -51,8 +51,14 @@ typedef struct {
 
 typedef enum {
   HAWKES_FP64 = 0,  /* every step in float64; exp from the device math library */
-  HAWKES_MIXED = 1  /* pair arithmetic and exp in float32, all sums, logs, the
+  HAWKES_MIXED = 1, /* pair arithmetic and exp in float32, all sums, logs, the
                        compensator and final reductions in float64 */
+  HAWKES_CULL = 0x10 /* flag, OR-ed into either precision: skip the column tiles
+                        whose every pair is so far apart in time that both pair
+                        terms are exactly zero in that precision's arithmetic
+                        (float64: exponents below -750; mixed: base-2 exponents
+                        below -160 after the shift).  Results are bitwise equal
+                        to the run without the flag; only time changes. */
 } hawkes_prec_t;
 
 typedef enum {

@@ -12,6 +12,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "hawkes.h")
 
 OK, EINVAL, EPARAM, EDATA, EZERORATE, ENOMEM, EDEVICE, ESTATE, ETIMEOUT, EPENDING = 0, -1, -2, -3, -4, -5, -6, -7, -8, 1
 FP64, MIXED = 0, 1
+CULL = 0x10   # flag OR-ed into a precision: exact time culling of far tiles
 
 
 class HawkesParams(ctypes.Structure):

@@ -12,14 +12,17 @@ import torch
 from . import _lib
 from ._lib import FP64, MIXED, HawkesError, HawkesParams
 
-PRECISIONS = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
+PRECISIONS = {"fp64": FP64, "mixed": MIXED, "fp64+cull": FP64 | _lib.CULL, "mixed+cull": MIXED | _lib.CULL,
+              FP64: FP64, MIXED: MIXED, FP64 | _lib.CULL: FP64 | _lib.CULL, MIXED | _lib.CULL: MIXED | _lib.CULL}
 
 
 def _prec(p) -> int:
+    """'fp64' or 'mixed', optionally with '+cull' (exact culling of tiles whose
+    pair terms all underflow; bitwise the same results)."""
     try:
         return PRECISIONS[p]
     except KeyError:
-        raise ValueError(f"precision must be 'fp64' or 'mixed', got {p!r}")
+        raise ValueError(f"precision must be 'fp64', 'mixed', 'fp64+cull' or 'mixed+cull', got {p!r}")
 
 
 def params_struct(params: Sequence[float]) -> HawkesParams:

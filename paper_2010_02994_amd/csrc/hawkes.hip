@@ -39,11 +39,13 @@ static int tiles_per_item(int64_t n) {
 }
 
 bool make_layout(int64_t n, int d, int prec, Layout& Lo) {
-  if (n < 2 || n > (int64_t(1) << 30) || d < 1 || d > kMaxD || (prec != HAWKES_FP64 && prec != HAWKES_MIXED))
+  const int base = prec & ~HAWKES_CULL;
+  if (n < 2 || n > (int64_t(1) << 30) || d < 1 || d > kMaxD || (base != HAWKES_FP64 && base != HAWKES_MIXED))
     return false;
   Lo.n = n;
   Lo.d = d;
-  Lo.mixed = prec == HAWKES_MIXED;
+  Lo.mixed = base == HAWKES_MIXED;
+  Lo.cull = (prec & HAWKES_CULL) != 0;
   Lo.nb = (int)((n + kBandRows - 1) / kBandRows);
   Lo.n_pad = Lo.nb * kBandRows;
   Lo.L = tiles_per_item(n);
@@ -150,6 +152,20 @@ KParams make_kparams(const Layout& Lo, const hawkes_params_t* p) {
   k.S = (float)S;
   k.sigma_main = -S * std::log(2.0);
   k.flag_floor = Lo.mixed ? kFloorMixed : kFloorFp64;
+  // Culling distances, ignoring the spatial parts of the exponents (which
+  // only lower them).  Mixed: both base-2 exponents S - mB dt^2 and S - mW dt
+  // (dt in units of tau_t) below -160, where exp2 is 0 to any rounding.
+  // Float64: both natural exponents -beta dt^2 and -omega dt below -750,
+  // where exp is 0.
+  k.cull = Lo.cull;
+  if (Lo.mixed) {
+    const double lim = S + 160.0;
+    k.cull_dtf = (float)std::max(std::sqrt(lim / (double)k.mB), lim / (double)k.mW);
+    k.cull_dt = (double)k.cull_dtf * k.tau_t;
+  } else {
+    k.cull_dt = std::max(std::sqrt(750.0 / k.beta), 750.0 / k.omega);
+    k.cull_dtf = (float)(k.cull_dt / k.tau_t);
+  }
   return k;
 }
 

@@ -64,6 +64,11 @@ struct KParams {
   double inv_tx, inv_tt;      // 1/tau_x, 1/tau_t (packing scales)
   double sigma_main;          // natural log of the scale the main pass sums carry (-S ln 2, or 0)
   double flag_floor;          // a row is recomputed when lambda~ < cmax * 2^flag_floor
+  // exact culling (optional): a column tile whose every pair is further apart
+  // in time than cull_dt (in the records' time units) adds exactly zero
+  int cull;
+  float cull_dtf;             // mixed records: bandwidth units of tau_t
+  double cull_dt;             // float64 records: time units
 };
 
 // One request of a launch: its constants, its inputs and outputs, the pieces

@@ -81,6 +81,20 @@ __device__ __forceinline__ HK_GLOBAL T* glb(T* p) {
 }
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Exact culling: every pair of the band's rows with this column tile lies
+// further apart in time than kp.cull_dt, so both pair terms are exactly zero
+// in this pass's arithmetic.  Records are time-sorted, so the band's first row
+// and the tile's last column bound every pair's time difference.
+template <int D, bool MIX, typename RecPtr>
+__device__ __forceinline__ bool tile_culled(RecPtr rec, int row_base, int tile, const KParams& kp) {
+  if (!kp.cull) return false;
+  const int last = min(kp.n - 1, tile * kTile + kTile - 1);
+  bool c;
+  if constexpr (MIX) c = (float)rec[row_base].v[D] - (float)rec[last].v[D] > kp.cull_dtf;
+  else c = (double)rec[row_base].v[D] - (double)rec[last].v[D] > kp.cull_dt;
+  return uni(c ? 1 : 0) != 0;
+}
+
 // Which request of a batched launch owns block `blk`: the last request whose
 // first block (offsets are non-decreasing) is <= blk.  kind 0: pair-pass
 // items, 1: per-event blocks, 2: pack blocks.
@@ -356,8 +370,13 @@ __global__ void __launch_bounds__(kThreads) k_pass1(const ReqDesc* __restrict__ 
       pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
     }
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
-    if (full) pass1_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
-    else pass1_tile<D, MIX, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    if (tile_culled<D, MIX>(rec, row_base, tile, kp)) {
+      // nothing to add: the tile's column sums stay zero
+    } else if (full) {
+      pass1_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    } else {
+      pass1_tile<D, MIX, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    }
 
   }
   __syncthreads();
@@ -502,8 +521,13 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ 
       pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
     }
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
-    if (full) pass2_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
-    else pass2_tile<D, MIX, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    if (tile_culled<D, MIX>(rec, row_base, tile, kp)) {
+      // nothing to add: the tile's column sums stay zero
+    } else if (full) {
+      pass2_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    } else {
+      pass2_tile<D, MIX, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    }
 
   }
   __syncthreads();
@@ -645,8 +669,15 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H
       pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
     }
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
-    if (full) pass1_tile_mixed<D, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
-    else pass1_tile_mixed<D, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    if (tile_culled<D, true>(rec, row_base, tile, kp)) {
+      // the tile adds exactly zero: its column sums are zero
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) s_acc[buf][wave][q][lane] = 0.f;
+    } else if (full) {
+      pass1_tile_mixed<D, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    } else {
+      pass1_tile_mixed<D, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -774,8 +805,15 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H
       pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
     }
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
-    if (full) pass2_tile_mixed<D, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
-    else pass2_tile_mixed<D, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    if (tile_culled<D, true>(rec, row_base, tile, kp)) {
+      // the tile adds exactly zero: its column sums are zero
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) s_acc[buf][wave][q][lane] = 0.f;
+    } else if (full) {
+      pass2_tile_mixed<D, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    } else {
+      pass2_tile_mixed<D, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll

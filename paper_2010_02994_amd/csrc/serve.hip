@@ -248,7 +248,7 @@ bool admit_and_launch(hawkes_server* S) {
       if (hipMemcpyAsync(b.dev_desc, b.host_desc, sizeof(ReqDesc) * b.nreq, hipMemcpyHostToDevice, b.stream) !=
           hipSuccess)
         st = HAWKES_EDEVICE;
-      if (st == HAWKES_OK) st = launch_batch(cls_d, cls_p == HAWKES_MIXED, b.dev_desc, b.nreq, g, grad, b.stream);
+      if (st == HAWKES_OK) st = launch_batch(cls_d, (cls_p & ~HAWKES_CULL) == HAWKES_MIXED, b.dev_desc, b.nreq, g, grad, b.stream);
       if (st == HAWKES_OK &&
           hipMemcpyAsync(b.host_out, b.dev_out, sizeof(double) * 8 * b.nreq, hipMemcpyDeviceToHost, b.stream) !=
               hipSuccess)
@@ -379,7 +379,7 @@ int hawkes_serve_submit(hawkes_server_t* S, int32_t dataset_id, const double* x,
                         double* grad_x, uint64_t* ticket) {
   using namespace hawkes;
   if (!S || !x || !p || !ticket) return HAWKES_EINVAL;
-  if (prec != HAWKES_FP64 && prec != HAWKES_MIXED) return HAWKES_EINVAL;
+  if ((prec & ~HAWKES_CULL) != HAWKES_FP64 && (prec & ~HAWKES_CULL) != HAWKES_MIXED) return HAWKES_EINVAL;
   if (!valid_params(p)) return HAWKES_EPARAM;
   std::lock_guard<std::mutex> lk(S->mu);
   if (S->stop) return HAWKES_ESTATE;

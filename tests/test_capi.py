@@ -21,6 +21,10 @@ def test_workspace_bytes_rules():
     assert L.hawkes_workspace_bytes(100, 0, 1) == 0
     assert L.hawkes_workspace_bytes(100, 9, 1) == 0
     assert L.hawkes_workspace_bytes(100, 2, 7) == 0
+    # the culling flag changes no buffer; other flag bits are rejected
+    assert L.hawkes_workspace_bytes(1000, 2, 1 | 0x10) == L.hawkes_workspace_bytes(1000, 2, 1)
+    assert L.hawkes_workspace_bytes(1000, 2, 0 | 0x10) == L.hawkes_workspace_bytes(1000, 2, 0)
+    assert L.hawkes_workspace_bytes(1000, 2, 1 | 0x20) == 0
     a = L.hawkes_workspace_bytes(50000, 2, 1)
     b = L.hawkes_workspace_bytes(50000, 2, 0)
     assert 0 < a < b < 1 << 30

@@ -279,3 +279,16 @@ def test_concurrent_callers_on_own_streams(prec):
         for r in range(3):
             a, b = out[k][r], alone[k]
             assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2]), (k, r)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_exact_culling_is_bitwise_identical(prec):
+    """A window much longer than the temporal scales: most column tiles lie so
+    far in the past that both pair terms are exactly zero and are skipped; every
+    output is bit for bit the one of the all-pairs run, and matches the oracle."""
+    w = W.random_case(71, 6000, 2, ties=3, t_span=20000.0)
+    say(f"case exact culling prec={prec} params={np.round(w.params, 3).tolist()}")
+    a = run_gpu(w.x, w.t, w.params, prec)
+    b = run_gpu(w.x, w.t, w.params, prec + "+cull")
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    check(prec, *b, *_oracle(w.x, w.t, w.params), w.params, w.n, label="culled")
