@@ -68,11 +68,16 @@ def measured_traffic(kernel_prefix: str, workload: str):
     return None
 
 
-def pass_work(d: int, which: str):
+def pass_work(d: int, which: str, prec: str = "mixed"):
     """Algorithmic work per unordered pair: (FLOPs with FMA = 2, exps).
-    Rate pass: differences (D+1), r^2 (2D-1), dt^2 (1), two exponents (8),
-    nine accumulations (15).  Gradient pass: recompute (3D+9), weights (6),
-    two-sided scatter (4D)."""
+    Float64 path -- rate pass: differences (D+1), r^2 (2D-1), dt^2 (1), two
+    exponents (8), nine accumulations (15); gradient pass: recompute (3D+9),
+    weights (6), two-sided scatter (4D).  Mixed gradient calls move the two
+    background moments (r^2 and dt^2 sums, row and column: 8) out of the rate
+    pass (3D+16) and form their gradient terms in the gradient pass as two
+    weighted sums (4): 7D+19."""
+    if prec.startswith("mixed"):
+        return (3 * d + 16, 2) if which == "pass1" else (7 * d + 19, 2)
     return (3 * d + 24, 2) if which == "pass1" else (7 * d + 15, 2)
 
 
@@ -184,7 +189,7 @@ def main():
     # dominant kernel and its roofline (algorithmic work per launch / measured duration)
     pass_ms = {k: float(stage_ms[STAGES.index(k)]) for k in ("pass1", "pass2")}
     dom = max(pass_ms, key=pass_ms.get)
-    flops, exps = pass_work(d, dom)
+    flops, exps = pass_work(d, dom, args.prec)
     pairs_u = n * (n - 1) / 2
     work = pairs_u * (flops + exps * FLOP_EQ_PER_EXP)
     achieved = work / (pass_ms[dom] * 1e-3)
@@ -196,8 +201,8 @@ def main():
             "work_per_unordered_pair": {"flops": flops, "exps": exps, "flop_eq_per_exp": FLOP_EQ_PER_EXP},
             "kernel_ms": round(pass_ms[dom], 4)}
     # whole-path roofline: both passes' algorithmic work over the full step time
-    f1, e1 = pass_work(d, "pass1")
-    f2, e2 = pass_work(d, "pass2")
+    f1, e1 = pass_work(d, "pass1", args.prec)
+    f2, e2 = pass_work(d, "pass2", args.prec)
     path_work = pairs_u * (f1 + f2 + (e1 + e2) * FLOP_EQ_PER_EXP)
 
     mwg = mwg_bench(w, dev, args.mwg_steps) if args.mwg_steps > 0 else None

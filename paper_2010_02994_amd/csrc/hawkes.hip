@@ -81,6 +81,7 @@ bool make_layout(int64_t n, int d, int prec, Layout& Lo) {
   Lo.off_bpart = take(sizeof(double) * 8 * (size_t)Lo.nblk);
   Lo.off_gfix = take(sizeof(double) * (size_t)d * n);
   Lo.off_fixpart = take(sizeof(double) * 8 * kFixSeg * (size_t)n);
+  Lo.off_mompart = take(sizeof(double) * 2 * (size_t)Lo.items);
   Lo.total = o;
   return true;
 }
@@ -158,6 +159,7 @@ KParams make_kparams(const Layout& Lo, const hawkes_params_t* p) {
   // Float64: both natural exponents -beta dt^2 and -omega dt below -750,
   // where exp is 0.
   k.cull = Lo.cull;
+  k.ru1 = 1;
   if (Lo.mixed) {
     const double lim = S + 160.0;
     k.cull_dtf = (float)std::max(std::sqrt(lim / (double)k.mB), lim / (double)k.mW);
@@ -204,6 +206,10 @@ ReqDesc make_desc(const Layout& Lo, const KParams& kp, const double* x, const do
   r.bpart = at<double>(ws, Lo.off_bpart);
   r.gfix = at<double>(ws, Lo.off_gfix);
   r.fixpart = at<double>(ws, Lo.off_fixpart);
+  r.mompart = at<double>(ws, Lo.off_mompart);
+  // mixed gradient calls form the background moments' gradient terms in the
+  // gradient pass; every other call accumulates them in the rate pass
+  r.kp.ru1 = (Lo.mixed && grad_x != nullptr) ? 0 : 1;
   return r;
 }
 
@@ -285,8 +291,12 @@ static bool launch_phases(const ReqDesc* reqs, int nreq, const BatchGrid& g, boo
   mark(s, 1);
   k_pack<D, MIX><<<g.pad_blocks, kEvBlock, 0, s>>>(reqs, nreq);
   mark(s, 2);
-  if constexpr (MIX) k_pass1_mixed<D><<<g.items, kThreads, 0, s>>>(reqs, nreq);
-  else k_pass1<D, MIX><<<g.items, kThreads, 0, s>>>(reqs, nreq);
+  if constexpr (MIX) {
+    if (grad) k_pass1_mixed<D, false><<<g.items, kThreads, 0, s>>>(reqs, nreq);
+    else k_pass1_mixed<D, true><<<g.items, kThreads, 0, s>>>(reqs, nreq);
+  } else {
+    k_pass1<D, MIX><<<g.items, kThreads, 0, s>>>(reqs, nreq);
+  }
   mark(s, 3);
   k_reduce1<D, MIX><<<g.ev_blocks, kRedThreads, 0, s>>>(reqs, nreq);
   mark(s, 4);

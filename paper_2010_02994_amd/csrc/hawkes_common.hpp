@@ -67,6 +67,8 @@ struct KParams {
   // exact culling (optional): a column tile whose every pair is further apart
   // in time than cull_dt (in the records' time units) adds exactly zero
   int cull;
+  int ru1;                    // the rate pass accumulates the background moments R, U (else the gradient pass
+                              // forms their parameter-gradient terms; mixed gradient calls)
   float cull_dtf;             // mixed records: bandwidth units of tau_t
   double cull_dt;             // float64 records: time units
 };
@@ -100,6 +102,7 @@ struct ReqDesc {
   double* gfix;
   double* fixpart;
   double* terms;    // optional, n x 4: per-event terms written by k_final1 (null: none)
+  double* mompart;  // items x 2: per-item moment sums of the mixed gradient pass
   int blk_items;    // first block of this request in a pair-pass launch
   int blk_ev;       // first block in a per-event launch (kEvBlock events per block)
   int blk_pad;      // first block in the pack launch (n_pad / kEvBlock blocks)

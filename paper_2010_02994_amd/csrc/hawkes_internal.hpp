@@ -17,7 +17,7 @@ struct Layout {
   int nb = 0, n_pad = 0, L = 1, items = 0, nblk = 0;
   size_t off_desc, off_status, off_dconst, off_out8, off_items, off_band, off_rec, off_first, off_ps, off_prow,
       off_pcol, off_sums, off_sigma, off_flags, off_list, off_listpos, off_bcount, off_bstage, off_logl, off_bpart,
-      off_gfix, off_fixpart, total;
+      off_gfix, off_fixpart, off_mompart, total;
 };
 
 struct BatchGrid {

@@ -409,6 +409,8 @@ struct Pass2Rows {
   Real x[R][D], t[R], pb[R], ps[R];
   int first[R];
   Real g[R][D];
+  Real mom[2];        // mixed: per-tile sums of w r^2 and w dt^2 (w = background pair weight)
+  double momd[2];     // their float64 running sums
   double acc[R][D];
 };
 
@@ -560,7 +562,7 @@ __device__ __forceinline__ float rol1(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xf, 0xf, false));
 }
 
-template <int D, bool MASK>
+template <int D, bool MASK, bool RU>
 __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const typename Traits<D, true>::Rec* __restrict__ cols,
                                                  float* __restrict__ acc_w, int tile_base, const KParams& kp) {
   constexpr int R = kRowsPerLane;
@@ -590,34 +592,47 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
         es = act ? es : 0.f;
       }
       S.a[r][0] += eb;
-      S.a[r][1] = eb * r2 + S.a[r][1];
-      S.a[r][2] = eb * dt2 + S.a[r][2];
+      if (RU) {
+        S.a[r][1] = eb * r2 + S.a[r][1];
+        S.a[r][2] = eb * dt2 + S.a[r][2];
+      }
       S.a[r][3] += es;
       S.a[r][4] = es * r2 + S.a[r][4];
       S.a[r][5] = es * dt + S.a[r][5];
       // column contributions summed over this lane's rows (no "+ 0": a signed
       // zero keeps the compiler from folding it)
       cK = r == 0 ? eb : cK + eb;
-      cR = r == 0 ? eb * r2 : eb * r2 + cR;
-      cU = r == 0 ? eb * dt2 : eb * dt2 + cU;
+      if (RU) {
+        cR = r == 0 ? eb * r2 : eb * r2 + cR;
+        cU = r == 0 ? eb * dt2 : eb * dt2 + cU;
+      }
     }
     aK = rol1(aK) + cK;
-    aR = rol1(aR) + cR;
-    aU = rol1(aU) + cU;
+    if (RU) {
+      aR = rol1(aR) + cR;
+      aU = rol1(aU) + cU;
+    }
   }
   const int c = (lane + 63) & 63;
   acc_w[0 * 64 + c] = aK;
-  acc_w[1 * 64 + c] = aR;
-  acc_w[2 * 64 + c] = aU;
+  if (RU) {
+    acc_w[1 * 64 + c] = aR;
+    acc_w[2 * 64 + c] = aU;
+  }
 }
 
-template <int D>
+// RU: also accumulate the background moments R = sum e r^2 and U = sum e dt^2
+// (six row sums, three column sums).  Without RU (gradient calls) the rate
+// pass keeps K, J, V, W (four row sums, one column sum) and the gradient pass
+// forms the two moments' contributions to the parameter gradient instead.
+template <int D, bool RU>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HK_RATE_WAVES_PER_EU))) k_pass1_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
   using Rec = typename Traits<D, true>::Rec;
   using Real = float;
   using ColT = float;
   constexpr int R = kRowsPerLane;
-  constexpr int NQ = 3;
+  constexpr int NQ = RU ? 3 : 1;   // column sums
+  constexpr int QR = RU ? 6 : 4;   // row sums stored per item
   __shared__ Rec s_rec[2][2 * kTile];
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
   const int rid = find_req(reqs, nreq, blockIdx.x, 0);
@@ -674,9 +689,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H
 #pragma unroll
       for (int q = 0; q < NQ; ++q) s_acc[buf][wave][q][lane] = 0.f;
     } else if (full) {
-      pass1_tile_mixed<D, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+      pass1_tile_mixed<D, false, RU>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
     } else {
-      pass1_tile_mixed<D, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+      pass1_tile_mixed<D, true, RU>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -696,8 +711,10 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H
   for (int r = 0; r < R; ++r) {
     const int lr = wave * 64 * R + r * 64 + lane;
 #pragma unroll
-    for (int q = 0; q < 6; ++q)
-      glb(static_cast<float*>(rq.prow))[((int64_t)item * 6 + q) * kBandRows + lr] = (float)S.acc[r][q];
+    for (int q = 0; q < QR; ++q) {
+      const int src = RU ? q : (q == 0 ? 0 : q + 2);   // without RU: K, J, V, W
+      glb(static_cast<float*>(rq.prow))[((int64_t)item * QR + q) * kBandRows + lr] = (float)S.acc[r][src];
+    }
   }
 }
 
@@ -732,7 +749,13 @@ __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const ty
         eb = act ? eb : 0.f;
         es = act ? es : 0.f;
       }
-      const float coef = eb * (S.pb[r] + col.v[D + 1]) + es * S.ps[r];
+      // background weight of the pair with both endpoints' 1/lambda; its
+      // r^2 and dt^2 moments give the rate pass's R and U terms of the
+      // tau_x and tau_t gradients
+      const float wb = eb * (S.pb[r] + col.v[D + 1]);
+      const float coef = es * S.ps[r] + wb;
+      S.mom[0] = wb * r2 + S.mom[0];
+      S.mom[1] = wb * (dt * dt) + S.mom[1];
 #pragma unroll
       for (int q = 0; q < D; ++q) {
         S.g[r][q] = -coef * dx[q] + S.g[r][q];
@@ -756,6 +779,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H
   constexpr int NQ = D;
   __shared__ Rec s_rec[2][2 * kTile];
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
+  __shared__ double s_red[kThreads];
   const int rid = find_req(reqs, nreq, blockIdx.x, 0);
   const ReqDesc& rq = reqs[rid];
   if (uni(glb(rq.status)[kStData]) != 0) return;
@@ -775,6 +799,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H
   const int first_min = uni(first[row_base]);
 
   Pass2Rows<D, true> S;
+  S.mom[0] = S.mom[1] = 0.f;
+  S.momd[0] = S.momd[1] = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int gi = row_base + wave * 64 * R + r * 64 + lane;
@@ -818,6 +844,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int q = 0; q < D; ++q) { S.acc[r][q] += (double)S.g[r][q]; S.g[r][q] = 0.f; }
+    S.momd[0] += (double)S.mom[0];
+    S.momd[1] += (double)S.mom[1];
+    S.mom[0] = S.mom[1] = 0.f;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < NQ * kTile; e += kThreads) {
@@ -834,6 +863,13 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H
 #pragma unroll
     for (int q = 0; q < D; ++q)
       glb(static_cast<float*>(rq.prow))[((int64_t)item * D + q) * kBandRows + lr] = (float)S.acc[r][q];
+  }
+  // the item's two moment sums, fixed-order over the workgroup
+  const double m0 = block_sum_256(S.momd[0], s_red);
+  const double m1 = block_sum_256(S.momd[1], s_red);
+  if (threadIdx.x == 0) {
+    glb(rq.mompart)[(int64_t)item * 2 + 0] = m0;
+    glb(rq.mompart)[(int64_t)item * 2 + 1] = m1;
   }
 }
 
@@ -876,17 +912,29 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce1(const ReqDesc* __restri
     const int b = i / kBandRows, lr = i % kBandRows;
     const IPair bi{glb(rq.band)[b].x, glb(rq.band)[b].y};
     double s[6] = {0, 0, 0, 0, 0, 0};
-    for (int c = sub; c < bi.y; c += 4) {
-      const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * 6 * kBandRows + lr;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) s[q] += (double)p[(int64_t)q * kBandRows];
-    }
     const auto pcol = glb(static_cast<const ColT*>(rq.pcol));
-#pragma unroll 4
-    for (int I = b + sub; I < kp.nb; I += 4) {
-      const auto p = pcol + (int64_t)I * 3 * kp.n_pad + i;
+    if (!MIX || kp.ru1) {
+      for (int c = sub; c < bi.y; c += 4) {
+        const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * 6 * kBandRows + lr;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) s[q] += (double)p[(int64_t)q * kp.n_pad];
+        for (int q = 0; q < 6; ++q) s[q] += (double)p[(int64_t)q * kBandRows];
+      }
+#pragma unroll 4
+      for (int I = b + sub; I < kp.nb; I += 4) {
+        const auto p = pcol + (int64_t)I * 3 * kp.n_pad + i;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s[q] += (double)p[(int64_t)q * kp.n_pad];
+      }
+    } else {
+      // rate pass without the background moments: rows K, J, V, W, column K
+      for (int c = sub; c < bi.y; c += 4) {
+        const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * 4 * kBandRows + lr;
+        s[0] += (double)p[0];
+#pragma unroll
+        for (int q = 1; q < 4; ++q) s[q + 2] += (double)p[(int64_t)q * kBandRows];
+      }
+#pragma unroll 4
+      for (int I = b + sub; I < kp.nb; I += 4) s[0] += (double)pcol[(int64_t)I * kp.n_pad + i];
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) s[q] = quad_sum(s[q]);
@@ -1221,7 +1269,40 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce2(const ReqDesc* __restri
   const KParams& kp = rq.kp;
   const int sub = threadIdx.x & 3;
   const int i = (blockIdx.x - rq.blk_ev) * kEvBlock + (threadIdx.x >> 2);
-  if (uni(glb(rq.status)[kStData]) != 0 || rq.grad_x == nullptr) return;
+  if (uni(glb(rq.status)[kStData]) != 0) return;
+  if (MIX && !kp.ru1 && blockIdx.x == rq.blk_ev) {
+    // the background moments' terms of d ell/d tau_x and d ell/d tau_t, from
+    // the gradient pass's item sums in item order: sum over pairs of
+    // w r'^2 = sum_n c_bg R_n / (tau_x^3 lambda_n) and w dt'^2 tau_x / tau_t =
+    // sum_n c_bg U_n / (tau_t^3 lambda_n) over the unflagged rows (flagged
+    // rows carry their exact R and U from the fix-up instead)
+    __shared__ double s_mom[kRedThreads];
+    double m0 = 0.0, m1 = 0.0;
+    for (int it = threadIdx.x; it < kp.items; it += kRedThreads) {
+      m0 += glb(rq.mompart)[(int64_t)it * 2 + 0];
+      m1 += glb(rq.mompart)[(int64_t)it * 2 + 1];
+    }
+    s_mom[threadIdx.x] = m0;
+    __syncthreads();
+    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) s_mom[threadIdx.x] += s_mom[threadIdx.x + h];
+      __syncthreads();
+    }
+    m0 = s_mom[0];
+    __syncthreads();
+    s_mom[threadIdx.x] = m1;
+    __syncthreads();
+    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) s_mom[threadIdx.x] += s_mom[threadIdx.x + h];
+      __syncthreads();
+    }
+    m1 = s_mom[0];
+    if (threadIdx.x == 0 && glb(rq.out8)[7] == 0.0) {
+      glb(rq.out8)[2] += m0;
+      glb(rq.out8)[3] += m1 * kp.tau_x / kp.tau_t;
+    }
+  }
+  if (rq.grad_x == nullptr) return;
   const auto grad_x = glb(rq.grad_x);
   if (uni(glb(rq.status)[kStZero]) != 0) {
     if (i < kp.n && sub == 0)

@@ -243,6 +243,9 @@ bool admit_and_launch(hawkes_server* S) {
         b.host_desc[k] = make_desc(Lo, kp, r->x, ds.t, S->arena_base + r->off, b.dev_out + 8 * k, r->grad_x);
         grad = grad || r->grad_x != nullptr;
       }
+      // one rate-pass variant per batch: with a gradient pass, the mixed
+      // requests form the background moments there (with or without grad_x)
+      for (int k = 0; k < b.nreq; ++k) b.host_desc[k].kp.ru1 = (grad && b.host_desc[k].kp.mixed) ? 0 : 1;
       const BatchGrid g = assign_blocks(b.host_desc, b.nreq);
       int st = HAWKES_OK;
       if (hipMemcpyAsync(b.dev_desc, b.host_desc, sizeof(ReqDesc) * b.nreq, hipMemcpyHostToDevice, b.stream) !=
