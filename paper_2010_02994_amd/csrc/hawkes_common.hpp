@@ -19,6 +19,12 @@ namespace hawkes {
 #ifndef HK_GRAD_WAVES_PER_EU
 #define HK_GRAD_WAVES_PER_EU 7
 #endif
+#ifndef HK_RATE_EXP_STEPS
+#define HK_RATE_EXP_STEPS 2
+#endif
+#ifndef HK_GRAD_EXP_STEPS
+#define HK_GRAD_EXP_STEPS 1
+#endif
 constexpr int kWaves = HK_WAVES;        // waves per workgroup
 constexpr int kThreads = 64 * kWaves;   // workgroup size
 constexpr int kRowsPerLane = HK_ROWS_PER_LANE;  // rows each lane owns in the pair passes
@@ -27,6 +33,9 @@ constexpr int kTile = 64;               // columns per tile (one wave width)
 constexpr int kMaxD = 8;
 constexpr int kFixSeg = 16;             // partner segments per flagged row in the fix-up kernels
 constexpr int kEvBlock = 256;           // events per block of the per-event kernels
+// float32 pair passes: steps whose exps are issued together (rate, gradient)
+constexpr int kRateExpSteps = HK_RATE_EXP_STEPS;
+constexpr int kGradExpSteps = HK_GRAD_EXP_STEPS;
 
 // Plain pairs and 16-byte chunks (the HIP vector types cannot be used through
 // address-space-qualified pointers).

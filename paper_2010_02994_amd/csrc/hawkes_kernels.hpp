@@ -570,47 +570,72 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
   const float mA = kp.mA, mB = kp.mB, mG = kp.mG, mW = kp.mW, sh = kp.S;
   const typename Traits<D, true>::Rec* __restrict__ my = cols + lane;
   float aK = 0.f, aR = 0.f, aU = 0.f;
-#pragma unroll 8
-  for (int k = 0; k < 64; ++k) {
-    const auto col = my[k];
-    float cK, cR, cU;
+  // The exponents of kRateExpSteps consecutive steps are formed first and
+  // their exps issued back to back, so no exp result is consumed by the very
+  // next instruction; the steps are then accumulated in order.
+  constexpr int KS = kRateExpSteps;
+#pragma unroll (8 / KS)
+  for (int k0 = 0; k0 < 64; k0 += KS) {
+    float r2v[KS][R], dtv[KS][R], ebv[KS][R], esv[KS][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      float r2 = 0.f;
+    for (int s = 0; s < KS; ++s) {
+      const auto col = my[k0 + s];
 #pragma unroll
-      for (int q = 0; q < D; ++q) {
-        const float dx = S.x[r][q] - col.v[q];
-        r2 = q == 0 ? dx * dx : dx * dx + r2;
-      }
-      const float dt = S.t[r] - col.v[D];
-      const float dt2 = dt * dt;
-      float eb = __builtin_amdgcn_exp2f(__builtin_fmaf(-mB, dt2, __builtin_fmaf(-mA, r2, sh)));
-      float es = __builtin_amdgcn_exp2f(__builtin_fmaf(-mW, dt, __builtin_fmaf(-mG, r2, sh)));
-      if (MASK) {
-        const bool act = (tile_base + ((lane + k) & 63)) < S.first[r];
-        eb = act ? eb : 0.f;
-        es = act ? es : 0.f;
-      }
-      S.a[r][0] += eb;
-      if (RU) {
-        S.a[r][1] = eb * r2 + S.a[r][1];
-        S.a[r][2] = eb * dt2 + S.a[r][2];
-      }
-      S.a[r][3] += es;
-      S.a[r][4] = es * r2 + S.a[r][4];
-      S.a[r][5] = es * dt + S.a[r][5];
-      // column contributions summed over this lane's rows (no "+ 0": a signed
-      // zero keeps the compiler from folding it)
-      cK = r == 0 ? eb : cK + eb;
-      if (RU) {
-        cR = r == 0 ? eb * r2 : eb * r2 + cR;
-        cU = r == 0 ? eb * dt2 : eb * dt2 + cU;
+      for (int r = 0; r < R; ++r) {
+        float r2 = 0.f;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          const float dx = S.x[r][q] - col.v[q];
+          r2 = q == 0 ? dx * dx : dx * dx + r2;
+        }
+        const float dt = S.t[r] - col.v[D];
+        r2v[s][r] = r2;
+        dtv[s][r] = dt;
+        ebv[s][r] = __builtin_fmaf(-mB, dt * dt, __builtin_fmaf(-mA, r2, sh));
+        esv[s][r] = __builtin_fmaf(-mW, dt, __builtin_fmaf(-mG, r2, sh));
       }
     }
-    aK = rol1(aK) + cK;
-    if (RU) {
-      aR = rol1(aR) + cR;
-      aU = rol1(aU) + cU;
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        ebv[s][r] = __builtin_amdgcn_exp2f(ebv[s][r]);
+        esv[s][r] = __builtin_amdgcn_exp2f(esv[s][r]);
+      }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int k = k0 + s;
+      float cK, cR, cU;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float r2 = r2v[s][r], dt = dtv[s][r], dt2 = dt * dt;
+        float eb = ebv[s][r], es = esv[s][r];
+        if (MASK) {
+          const bool act = (tile_base + ((lane + k) & 63)) < S.first[r];
+          eb = act ? eb : 0.f;
+          es = act ? es : 0.f;
+        }
+        S.a[r][0] += eb;
+        if (RU) {
+          S.a[r][1] = eb * r2 + S.a[r][1];
+          S.a[r][2] = eb * dt2 + S.a[r][2];
+        }
+        S.a[r][3] += es;
+        S.a[r][4] = es * r2 + S.a[r][4];
+        S.a[r][5] = es * dt + S.a[r][5];
+        // column contributions summed over this lane's rows (no "+ 0": a
+        // signed zero keeps the compiler from folding it)
+        cK = r == 0 ? eb : cK + eb;
+        if (RU) {
+          cR = r == 0 ? eb * r2 : eb * r2 + cR;
+          cU = r == 0 ? eb * dt2 : eb * dt2 + cU;
+        }
+      }
+      aK = rol1(aK) + cK;
+      if (RU) {
+        aR = rol1(aR) + cR;
+        aU = rol1(aU) + cU;
+      }
     }
   }
   const int c = (lane + 63) & 63;
@@ -728,42 +753,63 @@ __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const ty
   float ag[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) ag[q] = 0.f;
-#pragma unroll 8
-  for (int k = 0; k < 64; ++k) {
-    const auto col = my[k];
-    float cgr[D];
+  // exponents of kGradExpSteps steps first, exps back to back, then the
+  // steps in order (as in the rate pass)
+  constexpr int KS = kGradExpSteps;
+#pragma unroll (8 / KS)
+  for (int k0 = 0; k0 < 64; k0 += KS) {
+    float dx[KS][R][D], r2[KS][R], dt[KS][R], eb[KS][R], es[KS][R], pbj[KS];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      float dx[D];
-      float r2 = 0.f;
+    for (int s = 0; s < KS; ++s) {
+      const auto col = my[k0 + s];
+      pbj[s] = col.v[D + 1];
 #pragma unroll
-      for (int q = 0; q < D; ++q) {
-        dx[q] = S.x[r][q] - col.v[q];
-        r2 = q == 0 ? dx[q] * dx[q] : dx[q] * dx[q] + r2;
-      }
-      const float dt = S.t[r] - col.v[D];
-      float eb = __builtin_amdgcn_exp2f(__builtin_fmaf(-mB, dt * dt, __builtin_fmaf(-mA, r2, sh)));
-      float es = __builtin_amdgcn_exp2f(__builtin_fmaf(-mW, dt, __builtin_fmaf(-mG, r2, sh)));
-      if (MASK) {
-        const bool act = (tile_base + ((lane + k) & 63)) < S.first[r];
-        eb = act ? eb : 0.f;
-        es = act ? es : 0.f;
-      }
-      // background weight of the pair with both endpoints' 1/lambda; its
-      // r^2 and dt^2 moments give the rate pass's R and U terms of the
-      // tau_x and tau_t gradients
-      const float wb = eb * (S.pb[r] + col.v[D + 1]);
-      const float coef = es * S.ps[r] + wb;
-      S.mom[0] = wb * r2 + S.mom[0];
-      S.mom[1] = wb * (dt * dt) + S.mom[1];
+      for (int r = 0; r < R; ++r) {
 #pragma unroll
-      for (int q = 0; q < D; ++q) {
-        S.g[r][q] = -coef * dx[q] + S.g[r][q];
-        cgr[q] = r == 0 ? coef * dx[q] : coef * dx[q] + cgr[q];
+        for (int q = 0; q < D; ++q) {
+          dx[s][r][q] = S.x[r][q] - col.v[q];
+          r2[s][r] = q == 0 ? dx[s][r][q] * dx[s][r][q] : dx[s][r][q] * dx[s][r][q] + r2[s][r];
+        }
+        dt[s][r] = S.t[r] - col.v[D];
+        eb[s][r] = __builtin_fmaf(-mB, dt[s][r] * dt[s][r], __builtin_fmaf(-mA, r2[s][r], sh));
+        es[s][r] = __builtin_fmaf(-mW, dt[s][r], __builtin_fmaf(-mG, r2[s][r], sh));
       }
     }
 #pragma unroll
-    for (int q = 0; q < D; ++q) ag[q] = rol1(ag[q]) + cgr[q];
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        eb[s][r] = __builtin_amdgcn_exp2f(eb[s][r]);
+        es[s][r] = __builtin_amdgcn_exp2f(es[s][r]);
+      }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int k = k0 + s;
+      float cgr[D];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        float ebr = eb[s][r], esr = es[s][r];
+        if (MASK) {
+          const bool act = (tile_base + ((lane + k) & 63)) < S.first[r];
+          ebr = act ? ebr : 0.f;
+          esr = act ? esr : 0.f;
+        }
+        // background weight of the pair with both endpoints' 1/lambda; its
+        // r^2 and dt^2 moments give the rate pass's R and U terms of the
+        // tau_x and tau_t gradients
+        const float wb = ebr * (S.pb[r] + pbj[s]);
+        const float coef = esr * S.ps[r] + wb;
+        S.mom[0] = wb * r2[s][r] + S.mom[0];
+        S.mom[1] = wb * (dt[s][r] * dt[s][r]) + S.mom[1];
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          S.g[r][q] = -coef * dx[s][r][q] + S.g[r][q];
+          cgr[q] = r == 0 ? coef * dx[s][r][q] : coef * dx[s][r][q] + cgr[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < D; ++q) ag[q] = rol1(ag[q]) + cgr[q];
+    }
   }
   const int c = (lane + 63) & 63;
 #pragma unroll
