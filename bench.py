@@ -29,7 +29,7 @@ METRIC = "pair-interactions/s for Hawkes loglik+grad (FP64 vs mixed); serve p50/
 STAGES = ["prep", "pack", "pass1", "reduce1", "flaglist", "fix1", "final1", "final2", "pass2", "fix2b", "fix2a",
           "reduce2"]
 KERNEL_NAMES = {"pass1": "k_pass1", "pass2": "k_pass2"}
-PROFILED_NAMES = {("pass1", "mixed"): "hawkes::k_pass1_mixed<2>", ("pass2", "mixed"): "hawkes::k_pass2_mixed<2>",
+PROFILED_NAMES = {("pass1", "mixed"): "hawkes::k_pass1_mixed<2, false>", ("pass2", "mixed"): "hawkes::k_pass2_mixed<2>",
                   ("pass1", "fp64"): "hawkes::k_pass1<2, false>", ("pass2", "fp64"): "hawkes::k_pass2<2, false>"}
 
 # Peaks of the chip (256 CUs at 2.4 GHz).  FP32 vector: 157.3 TFLOP/s.  The
