@@ -189,8 +189,10 @@ bool harvest(hawkes_server* S) {
 }
 
 // Admit from the FIFO into free batch slots and launch.  The head request
-// decides the batch's (D, precision); later requests of another class wait
-// for a later batch.  A head request that does not fit in memory blocks
+// decides the batch's class (D, precision, with or without a location
+// gradient); later requests of another class wait for a later batch.  The
+// class fixes which rate-pass variant runs, so a request's arithmetic is the
+// same alone, in any batch and through the direct calls.  A head request that does not fit in memory blocks
 // admission until memory frees up (no overtaking by smaller requests of its
 // class), which keeps admission fair.
 bool admit_and_launch(hawkes_server* S) {
@@ -199,12 +201,13 @@ bool admit_and_launch(hawkes_server* S) {
     if (b.busy || S->pending.empty()) continue;
     std::vector<Request*> take;
     int cls_d = -1, cls_p = -1;
+    bool cls_g = false;
     for (auto it = S->pending.begin(); it != S->pending.end();) {
       Request* r = *it;
       const Dataset& ds = S->datasets[r->ds];
       if (S->active >= S->max_slots) break;
-      if (cls_d < 0) { cls_d = ds.d; cls_p = r->prec; }
-      if (ds.d != cls_d || r->prec != cls_p) { ++it; continue; }
+      if (cls_d < 0) { cls_d = ds.d; cls_p = r->prec; cls_g = r->grad_x != nullptr; }
+      if (ds.d != cls_d || r->prec != cls_p || (r->grad_x != nullptr) != cls_g) { ++it; continue; }
       size_t off;
       if (!S->arena.alloc(r->foot, &off)) {
         if (take.empty()) { cls_d = -1; }
@@ -243,9 +246,6 @@ bool admit_and_launch(hawkes_server* S) {
         b.host_desc[k] = make_desc(Lo, kp, r->x, ds.t, S->arena_base + r->off, b.dev_out + 8 * k, r->grad_x);
         grad = grad || r->grad_x != nullptr;
       }
-      // one rate-pass variant per batch: with a gradient pass, the mixed
-      // requests form the background moments there (with or without grad_x)
-      for (int k = 0; k < b.nreq; ++k) b.host_desc[k].kp.ru1 = (grad && b.host_desc[k].kp.mixed) ? 0 : 1;
       const BatchGrid g = assign_blocks(b.host_desc, b.nreq);
       int st = HAWKES_OK;
       if (hipMemcpyAsync(b.dev_desc, b.host_desc, sizeof(ReqDesc) * b.nreq, hipMemcpyHostToDevice, b.stream) !=

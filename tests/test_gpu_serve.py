@@ -25,12 +25,19 @@ def data():
 
 
 def _run_set(server, ids, data, reqs, together):
-    """reqs: list of (dataset index, prec).  Returns [(status, ll, gp, grad_x numpy)]."""
+    """reqs: list of (dataset index, prec).  Returns [(status, ll, gp, grad_x numpy)].
+    Together: a float64 request on the largest dataset is submitted first and
+    holds the server's stream while the others queue, so they are batched
+    whatever the host's submission speed."""
     outs = [torch.full_like(data[k][1], float("nan")) for k, _ in reqs]
     res = [None] * len(reqs)
     if together:
+        big = max(range(len(data)), key=lambda k: data[k][0].n)
+        blocker = server.submit(ids[big], data[big][1], data[big][0].params, prec="fp64",
+                                grad_x=torch.empty_like(data[big][1]))
         tks = [server.submit(ids[k], data[k][1], data[k][0].params, prec=p, grad_x=outs[j])
                for j, (k, p) in enumerate(reqs)]
+        assert server.wait(blocker, 60)["status"] == 0
         for j, tk in enumerate(tks):
             res[j] = server.wait(tk, 60)
     else:
@@ -42,14 +49,15 @@ def _run_set(server, ids, data, reqs, together):
 
 def test_alone_vs_mix_bitwise_and_direct_call(data):
     reqs = [(k, p) for k in range(len(SIZES)) for p in ("mixed", "fp64")]
-    with Server(hbm_budget_bytes=4 << 30, max_slots=64, streams=3) as s:
+    with Server(hbm_budget_bytes=4 << 30, max_slots=64, streams=1) as s:
         ids = [s.register(d[2], 2) for d in data]
         say("case serve alone")
         alone = _run_set(s, ids, data, reqs, together=False)
         say("case serve mix")
         mix = _run_set(s, ids, data, reqs, together=True)
         st = s.stats()
-    assert st["batches_launched"] < len(reqs) * 2      # the mix shared batches
+    # alone: one batch per request; the mix (after the blocker) shares batches
+    assert st["batches_launched"] < len(reqs) * 2 + 1
     for (k, p), a, m in zip(reqs, alone, mix):
         assert a[0] == 0 and m[0] == 0
         assert a[1] == m[1] and np.array_equal(a[2], m[2]) and np.array_equal(a[3], m[3]), (k, p)
@@ -62,6 +70,31 @@ def test_alone_vs_mix_bitwise_and_direct_call(data):
         for p in ("mixed", "fp64"):
             j = reqs.index((k, p))
             check(p, alone[j][1], alone[j][3], alone[j][2], ll_ref, gx_ref, gp_ref, w.params, w.n, label=f"serve{k}")
+
+
+def test_requests_without_gradient_match_the_direct_call(data):
+    """Requests with no location gradient (log-likelihood and parameter
+    gradients only), submitted interleaved with gradient requests, equal the
+    direct enqueue-only call with grad_x = NULL bit for bit."""
+    with Server(hbm_budget_bytes=4 << 30, max_slots=64, streams=3) as s:
+        ids = [s.register(d[2], 2) for d in data]
+        say("case serve requests without gradient")
+        outs = {k: torch.full_like(data[k][1], float("nan")) for k in (0, 3)}
+        plan = [(0, None), (1, None), (0, "g"), (3, None), (3, "g"), (2, None)]
+        tks = [s.submit(ids[k], data[k][1], data[k][0].params, prec="mixed",
+                        grad_x=(outs[k] if g else None)) for k, g in plan]
+        res = [s.wait(tk, 60) for tk in tks]
+    torch.cuda.synchronize()
+    for (k, g), r in zip(plan, res):
+        w, x, t = data[k]
+        assert r["status"] == 0
+        if g:
+            ll, gx, gp = api.grad(x, t, w.params, prec="mixed")
+            assert np.array_equal(gx.cpu().numpy(), outs[k].cpu().numpy()), k
+        else:
+            out8 = api.grad_async(x, t, w.params, prec="mixed").cpu().numpy()
+            ll, gp = out8[0], out8[1:7]
+        assert r["loglik"] == ll and np.array_equal(np.array(r["grad_params"]), gp), (k, g)
 
 
 def test_bad_request_fails_alone(data):

@@ -104,3 +104,15 @@ def test_destroy_drains_queued_work():
     t0 = time.perf_counter()
     s.close()                                  # returns only after all 8 completed
     assert time.perf_counter() - t0 >= 4 * 3.6e-3 * 0.9
+
+
+def test_batches_are_homogeneous_in_the_gradient_flag():
+    """Requests with and without a location gradient never share a batch (the
+    rate-pass variant depends on it), so with one stream and alternating
+    submissions every request starts a batch of its own class."""
+    with Server(hbm_budget_bytes=1 << 30, max_slots=64, streams=1, simulate=True) as s:
+        d2 = s.register(1, 2, n=3000)
+        tks = [s.submit(d2, 1, P, "mixed", grad_x=(1 if k % 2 else None)) for k in range(6)]
+        res = [s.wait(tk, 10) for tk in tks]
+        assert all(r["status"] == 0 for r in res)
+        assert s.stats()["batches_launched"] >= 2
