@@ -17,7 +17,7 @@ namespace hawkes {
 #define HK_RATE_WAVES_PER_EU 5
 #endif
 #ifndef HK_GRAD_WAVES_PER_EU
-#define HK_GRAD_WAVES_PER_EU 7
+#define HK_GRAD_WAVES_PER_EU 6
 #endif
 #ifndef HK_RATE_EXP_STEPS
 #define HK_RATE_EXP_STEPS 2
