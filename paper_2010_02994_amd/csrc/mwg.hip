@@ -25,7 +25,8 @@ namespace hawkes {
 namespace mwg {
 
 constexpr int kBlock = 256;
-constexpr int kSeg = 32;          // partner segments per exactly recomputed row
+constexpr int kSeg = 32;          // partner segments per exactly recomputed row (workspace per event)
+constexpr int kMaxSeg = 512;      // at most, when few rows are listed
 constexpr int kExactGrid = 512;   // workgroups of the exact-row kernel (grid-stride over tasks)
 constexpr int kListThreads = 1024;
 
@@ -55,7 +56,7 @@ struct Step {
   int* bcount;          // nrb: rows of the block needing an exact recompute
   int* stage;           // nrb x kBlock: those rows in index order
   int* list;            // n: all of them in index order
-  double* part;         // n x kSeg x 2: segment sums (a, b) of each listed row
+  double* part;         // n x kSeg x 2: segment sums (a, b) of the listed rows
   int* state;           // [accepted, list length]
 };
 
@@ -217,6 +218,16 @@ __global__ void __launch_bounds__(kListThreads) k_mwg_list(Step s) {
   if (tid == kListThreads - 1) s.state[1] = s_scan[kListThreads - 1];
 }
 
+// Partner segments per listed row: kSeg, or more when few rows are listed so
+// that the tasks still spread over the grid (never more partials than the
+// workspace holds: kSeg per event).
+__device__ __forceinline__ int segs_for(int cnt, int n) {
+  int segs = kSeg;
+  while (segs < kMaxSeg && (int64_t)cnt * segs * 2 <= kExactGrid && (int64_t)cnt * segs * 2 <= (int64_t)n * kSeg)
+    segs *= 2;
+  return segs;
+}
+
 // Exact rows, split into (row, partner segment) tasks over a fixed grid: sums
 // of the row's pair terms against one segment of partners, every event at its
 // proposed place; a moved row sits at its proposed location.
@@ -224,9 +235,10 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_mwg_exact(Step s) {
   __shared__ double sh[kBlock];
   const int cnt = s.state[1];
-  const int seg = (s.n + kSeg - 1) / kSeg;
-  for (int64_t task = blockIdx.x; task < (int64_t)cnt * kSeg; task += gridDim.x) {
-    const int e = (int)(task / kSeg), sg = (int)(task % kSeg);
+  const int segs = segs_for(cnt, s.n);
+  const int seg = (s.n + segs - 1) / segs;
+  for (int64_t task = blockIdx.x; task < (int64_t)cnt * segs; task += gridDim.x) {
+    const int e = (int)(task / segs), sg = (int)(task % segs);
     const int r = s.list[e];
     const int rpos = s.flag[r] == 2 ? find_moved(s.idx, s.nmove, r) : -1;
     double xr[D];
@@ -249,14 +261,16 @@ __global__ void __launch_bounds__(kBlock) k_mwg_exact(Step s) {
     a = block_sum(a, sh);
     b = block_sum(b, sh);
     if (threadIdx.x == 0) {
-      s.part[((int64_t)e * kSeg + sg) * 2 + 0] = a;
-      s.part[((int64_t)e * kSeg + sg) * 2 + 1] = b;
+      s.part[((int64_t)e * segs + sg) * 2 + 0] = a;
+      s.part[((int64_t)e * segs + sg) * 2 + 1] = b;
     }
   }
 }
 
 // One workgroup: checks the moved list, merges the exact rows' segments in a
-// fixed order, sums the log-rate changes in a fixed order, decides.
+// fixed order, sums the log-rate changes in a fixed order, decides.  (A
+// separate launch: a device-wide fence in every workgroup of the exact kernel
+// would write back the L2 of each die, which costs more than the launch.)
 __global__ void __launch_bounds__(kListThreads) k_mwg_decide(Step s, int D) {
   __shared__ double sh[kListThreads];
   __shared__ int s_bad;
@@ -269,19 +283,30 @@ __global__ void __launch_bounds__(kListThreads) k_mwg_decide(Step s, int D) {
     if (bad) atomicOr(&s_bad, 1);
   }
   const int cnt = s.state[1];
+  const int segs = segs_for(cnt, s.n);
+  // one wave per listed row: its lanes add strided segments, a butterfly
+  // combines them (the same fixed order every time), lane 0 keeps the row's
+  // log-rate change in its running sum
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double acc = 0.0;
-  for (int e = threadIdx.x; e < cnt; e += kListThreads) {
-    const int r = s.list[e];
+  for (int e = wave; e < cnt; e += kListThreads / 64) {
     double a = 0.0, b = 0.0;
-    for (int sg = 0; sg < kSeg; ++sg) {
-      a += s.part[((int64_t)e * kSeg + sg) * 2 + 0];
-      b += s.part[((int64_t)e * kSeg + sg) * 2 + 1];
+    for (int sg = lane; sg < segs; sg += 64) {
+      a += s.part[((int64_t)e * segs + sg) * 2 + 0];
+      b += s.part[((int64_t)e * segs + sg) * 2 + 1];
     }
-    const double dl = log(s.m.mu0 * a + s.m.theta * b) - s.terms[(int64_t)r * 4 + 2];
-    s.new_a[r] = a;
-    s.new_b[r] = b;
-    s.dlog[r] = dl;
-    acc += dl;
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o);
+      b += __shfl_xor(b, o);
+    }
+    if (lane == 0) {
+      const int r = s.list[e];
+      const double dl = log(s.m.mu0 * a + s.m.theta * b) - s.terms[(int64_t)r * 4 + 2];
+      s.new_a[r] = a;
+      s.new_b[r] = b;
+      s.dlog[r] = dl;
+      acc += dl;
+    }
   }
   for (int b = threadIdx.x; b < s.nrb; b += kListThreads) acc += s.bpart[b];
   const double tot = block_sum(acc, sh);
