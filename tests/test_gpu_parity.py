@@ -292,3 +292,39 @@ def test_exact_culling_is_bitwise_identical(prec):
     b = run_gpu(w.x, w.t, w.params, prec + "+cull")
     assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
     check(prec, *b, *_oracle(w.x, w.t, w.params), w.params, w.n, label="culled")
+
+
+@pytest.fixture(scope="module")
+def big_case():
+    """The wildfire-like generator at N = 300,000 (six times the benchmark
+    size; 9e10 ordered pairs): too large for the oracle, so it is checked
+    through identities that hold at any size and against a float64 oracle
+    evaluation of the compensator alone."""
+    w = W.config2(n=300000)
+    p = w.params
+    T = w.t.max()
+    from scipy import stats
+    comp = (p[0] * (stats.norm.cdf((T - w.t) / p[2]) - stats.norm.cdf(-w.t / p[2]))
+            + p[3] * (1 - np.exp(-p[4] * (T - w.t))))
+    return w, math.fsum(comp)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_largest_size_identities(big_case, prec):
+    """At N = 300,000: the location gradient sums to zero (translation), the
+    weights' Euler identity mu0 d/dmu0 + theta d/dtheta = N - sum Lambda_n holds,
+    and the two precisions agree."""
+    w, sum_comp = big_case
+    say(f"case N=300000 identities prec={prec}")
+    ll, gx, gp = run_gpu(w.x, w.t, w.params, prec)
+    assert np.all(np.isfinite(gx)) and math.isfinite(ll)
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    scale = np.abs(gx).sum(0)
+    assert np.all(np.abs(gx.sum(0)) <= (1e-11 if prec == "fp64" else 1e-6) * scale)
+    euler = w.params[0] * gp[0] + w.params[3] * gp[3]
+    say(f"  euler {euler:.10g} vs {w.n - sum_comp:.10g}")
+    assert abs(euler - (w.n - sum_comp)) <= tol * w.n
+    if prec == "mixed":
+        ll64, gx64, gp64 = run_gpu(w.x, w.t, w.params, "fp64")
+        assert abs(ll - ll64) <= 1e-5 * abs(ll64)
+        assert np.linalg.norm(gx - gx64) <= 1e-4 * np.linalg.norm(gx64)
