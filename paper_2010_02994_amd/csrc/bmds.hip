@@ -55,8 +55,9 @@ struct Args {
 };
 
 // Wave totals in lane 63: inclusive row scans by DPP row_shr 1, 2, 4, 8, then
-// row_bcast:15 into rows 1 and 3 and row_bcast:31 into rows 2 and 3; lanes
-// without a source read 0.
+// row_bcast:15 (lane 63 gains lane 47, row 2's total) and row_bcast:31 (lane
+// 63 gains lane 31, by then rows 0 and 1's total); lanes without a source
+// read 0.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ float dpp_f(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, true));
@@ -85,10 +86,12 @@ __device__ __forceinline__ void wave_totals_lane63(R* v) {
   for (int k = 0; k < K; ++k) v[k] += dpp_step<0x114, 0xf>(v[k]);  // row_shr:4
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] += dpp_step<0x118, 0xf>(v[k]);  // row_shr:8
+  // all rows enabled: rows 0 and 1 may pick up other values, but lane 63
+  // only ever reads lane 47 (row 2's scan) and lane 31 (rows 0 and 1's total)
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x142, 0xa>(v[k]);  // row_bcast:15
+  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x142, 0xf>(v[k]);  // row_bcast:15
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x143, 0xc>(v[k]);  // row_bcast:31
+  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x143, 0xf>(v[k]);  // row_bcast:31
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -183,13 +186,18 @@ __global__ void __launch_bounds__(kThreads) k_bmds_tiles(Args a) {
   __syncthreads();
   const int rows = min(kTR, a.n - i0);
   for (int r0 = 0; r0 < rows; r0 += kPrefetch) {
-    // the next rows' entries first, so kPrefetch loads are in flight at once
+    // the next rows' entries first, so kPrefetch loads are in flight at once;
+    // every load is issued (its address clamped into the matrix) and the
+    // entries outside the triangle are masked afterwards, so no branch
+    // separates the loads and each row waits only for its own entry
     double v[kPrefetch];
+    const int jc = min(j, a.n - 1);
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) {
-      const int i = i0 + r0 + u;
-      v[u] = (r0 + u < rows && j < i) ? a.delta[(int64_t)i * a.n + j] : (double)NAN;
+      const int i = min(i0 + r0 + u, a.n - 1);
+      v[u] = a.delta[(int64_t)i * a.n + jc];
     }
+
 #pragma unroll
     for (int u = 0; u < kPrefetch; ++u) {
       const int r = r0 + u;
@@ -197,7 +205,7 @@ __global__ void __launch_bounds__(kThreads) k_bmds_tiles(Args a) {
       R gi[D];
 #pragma unroll
       for (int q = 0; q < D; ++q) gi[q] = R(0);
-      if (!isnan(v[u])) {
+      if (j < i0 + r && !isnan(v[u])) {
         if (v[u] < 0.0 || isinf(v[u])) {
           bad += 1;
         } else {
