@@ -324,9 +324,24 @@ def leapfrog_bench(dev, trajectories: int):
         torch.cuda.synchronize()
         el = (time.perf_counter() - t0) / trajectories
         inside = bool(((x >= lo) & (x <= hi)).all().item())
+        # the same trajectory captured once in a HIP graph and replayed: the
+        # launch overhead of ~250 kernels per trajectory leaves the host
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            api.leapfrog(x, p, t, w.params, eps, steps, prec=prec, bound="box", b0=lo, b1=hi,
+                         grad_x=g, have_grad=True, out8=out8)
+        graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(trajectories):
+            graph.replay()
+        torch.cuda.synchronize()
+        elg = (time.perf_counter() - t0) / trajectories
         out[prec] = {"ms_per_trajectory": el * 1e3, "ms_per_step": el * 1e3 / steps,
                      "pair_interactions_per_s": steps * w.n * (w.n - 1) / el,
+                     "graph_ms_per_trajectory": elg * 1e3,
                      "status": float(out8[7].item()), "inside_cells": inside}
+        del graph
     return out
 
 

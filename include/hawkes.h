@@ -91,7 +91,11 @@ int hawkes_loglik(const double* x, const double* t, int64_t n, int d, const hawk
  * float64 fix-ups and the finalize kernels run there while the gradient pass
  * runs on `stream`, and `stream` waits for them before the last kernel, so to
  * the caller all of the call's work is ordered on `stream`.  Calls on one
- * stream must come from one thread at a time. */
+ * stream must come from one thread at a time.  The enqueue-only calls
+ * (hawkes_grad_async, hawkes_leapfrog, hawkes_mwg_step, hawkes_bmds) may be
+ * captured into a HIP graph: the side stream joins the capture through its
+ * events (while capturing, a call that finds no pooled side stream runs in
+ * order on `stream` instead of creating one). */
 int hawkes_grad(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p /* host */,
                 int prec, void* ws, size_t ws_bytes, void* stream,
                 double* loglik /* host or NULL */, double* grad_x /* device */, double* grad_params /* host or NULL */);

@@ -243,7 +243,10 @@ struct Fork {
 // pool per device, grown on demand, kept for the life of the process.
 class ForkPool {
  public:
-  Fork* take(int dev) {
+  // allow_create = false (the caller's stream is being captured into a
+  // graph, where creating a stream or event is not permitted): only a pooled
+  // fork is handed out, else none.
+  Fork* take(int dev, bool allow_create) {
     {
       std::lock_guard<std::mutex> lk(mu_);
       auto& v = free_[dev];
@@ -253,6 +256,7 @@ class ForkPool {
         return f;
       }
     }
+    if (!allow_create) return nullptr;
     Fork f{};
     const bool s_ok = hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) == hipSuccess;
     const bool r_ok = s_ok && hipEventCreateWithFlags(&f.ready, hipEventDisableTiming) == hipSuccess;
@@ -361,7 +365,11 @@ int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const Batc
   (void)hipGetLastError();
   int dev = -1;
   Fork* fk = nullptr;
-  if (grad && g_timer == nullptr && hipGetDevice(&dev) == hipSuccess) fk = fork_pool().take(dev);
+  if (grad && g_timer == nullptr && hipGetDevice(&dev) == hipSuccess) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+    fk = fork_pool().take(dev, !capturing);
+  }
   const bool ok = mixed ? dispatch_d<true>(d, dev_reqs, nreq, g, grad, s, fk)
                         : dispatch_d<false>(d, dev_reqs, nreq, g, grad, s, fk);
   if (fk) fork_pool().give(dev, fk);

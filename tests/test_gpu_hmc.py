@@ -98,3 +98,52 @@ def test_leapfrog_chained_trajectories():
     np.testing.assert_allclose(x.cpu().numpy(), xa, rtol=0, atol=1e-13)
     np.testing.assert_allclose(p.cpu().numpy(), pa, rtol=1e-12, atol=1e-12)
     assert np.array_equal(g.cpu().numpy(), ga) or np.allclose(g.cpu().numpy(), ga, rtol=1e-12)
+
+
+def test_leapfrog_graph_replay_matches_eager():
+    """A 5-step trajectory captured once in a HIP graph (through torch's
+    graph capture; the library's side stream joins the capture through its
+    events) and replayed three times, with eager work and synchronizations
+    between the replays, gives bit for bit the states of three eager
+    trajectories."""
+    import torch
+    from paper_2010_02994_amd import api
+    w, bound, b0, b1 = _case("cells")
+    rng = np.random.default_rng(106)
+    p0 = rng.standard_normal(w.x.shape)
+    t, lo, hi = _dev(w.t), _dev(b0), _dev(b1)
+    say("case leapfrog graph replay")
+    for prec in ("mixed", "fp64"):
+        # eager reference: first gradient, then three chained 5-step trajectories
+        x, p = _dev(w.x), _dev(p0)
+        g, _ = api.leapfrog(x, p, t, w.params, 0.004, 1, prec=prec, bound="box", b0=lo, b1=hi)
+        x0, p0d, g0 = x.clone(), p.clone(), g.clone()
+        eager = []
+        for _ in range(3):
+            g, out8 = api.leapfrog(x, p, t, w.params, 0.004, 5, prec=prec, bound="box", b0=lo, b1=hi,
+                                   grad_x=g, have_grad=True)
+            torch.cuda.synchronize()
+            eager.append((x.cpu().numpy(), p.cpu().numpy(), g.cpu().numpy(), out8.cpu().numpy()))
+        # graph: capture one trajectory on the same state buffers
+        xs, ps, gs = x0.clone(), p0d.clone(), g0.clone()
+        out8g = torch.empty(8, dtype=torch.float64, device="cuda:0")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):   # warm the capture stream's workspace outside the capture
+            api.leapfrog(xs.clone(), ps.clone(), t, w.params, 0.004, 1, prec=prec, bound="box", b0=lo, b1=hi,
+                         grad_x=gs.clone(), have_grad=True, out8=out8g)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            api.leapfrog(xs, ps, t, w.params, 0.004, 5, prec=prec, bound="box", b0=lo, b1=hi,
+                         grad_x=gs, have_grad=True, out8=out8g)
+        xs.copy_(x0); ps.copy_(p0d); gs.copy_(g0)
+        torch.cuda.synchronize()
+        for k in range(3):
+            graph.replay()
+            torch.cuda.synchronize()
+            got = (xs.cpu().numpy(), ps.cpu().numpy(), gs.cpu().numpy(), out8g.cpu().numpy())
+            _ = (xs * 2).sum().item()   # unrelated eager work between replays
+            for a, b in zip(got, eager[k]):
+                assert np.array_equal(a, b), (prec, k)
