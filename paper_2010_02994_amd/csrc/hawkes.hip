@@ -35,7 +35,12 @@ static int tiles_per_item(int64_t n) {
   const int nb = (int)((n + kBandRows - 1) / kBandRows);
   int64_t tiles = 0;
   for (int b = 0; b < nb; ++b) tiles += (std::min<int64_t>(n, (int64_t)(b + 1) * kBandRows) + kTile - 1) / kTile;
-  return (int)std::max<int64_t>(1, (tiles + kTargetItems - 1) / kTargetItems);
+  // about kTargetItems work items for a full chip; at small N, where that
+  // would leave one tile per item, up to four tiles per item (fewer row
+  // partials for the reductions to read; measured best at N = 4,000-10,000)
+  const int64_t fill = (tiles + kTargetItems - 1) / kTargetItems;
+  const int64_t small = std::min<int64_t>(4, (tiles + 159) / 160);
+  return (int)std::max<int64_t>(1, std::max(fill, small));
 }
 
 bool make_layout(int64_t n, int d, int prec, Layout& Lo) {

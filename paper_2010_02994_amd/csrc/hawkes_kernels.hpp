@@ -960,6 +960,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce1(const ReqDesc* __restri
     double s[6] = {0, 0, 0, 0, 0, 0};
     const auto pcol = glb(static_cast<const ColT*>(rq.pcol));
     if (!MIX || kp.ru1) {
+#pragma unroll 4
       for (int c = sub; c < bi.y; c += 4) {
         const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * 6 * kBandRows + lr;
 #pragma unroll
@@ -973,6 +974,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce1(const ReqDesc* __restri
       }
     } else {
       // rate pass without the background moments: rows K, J, V, W, column K
+#pragma unroll 4
       for (int c = sub; c < bi.y; c += 4) {
         const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * 4 * kBandRows + lr;
         s[0] += (double)p[0];
@@ -1362,6 +1364,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce2(const ReqDesc* __restri
   for (int q = 0; q < D; ++q) s[q] = 0.0;
   const int b = i / kBandRows, lr = i % kBandRows;
   const IPair bi{glb(rq.band)[b].x, glb(rq.band)[b].y};
+#pragma unroll 4
   for (int c = sub; c < bi.y; c += 4) {
     const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * D * kBandRows + lr;
 #pragma unroll
