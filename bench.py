@@ -26,8 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "pair-interactions/s for Hawkes loglik+grad (FP64 vs mixed); serve p50/p99 ms"
-STAGES = ["prep", "pack", "pass1", "reduce1", "flaglist", "fix1", "final1", "final2", "pass2", "fix2b", "fix2a",
-          "reduce2"]
+STAGES = ["prep", "pack", "pass1", "reduce1", "fix1", "final1", "pass2", "fix2", "reduce2"]
 KERNEL_NAMES = {"pass1": "k_pass1", "pass2": "k_pass2"}
 PROFILED_NAMES = {("pass1", "mixed"): "hawkes::k_pass1_mixed<2, false>", ("pass2", "mixed"): "hawkes::k_pass2_mixed<2>",
                   ("pass1", "fp64"): "hawkes::k_pass1<2, false>", ("pass2", "fp64"): "hawkes::k_pass2<2, false>"}
@@ -136,7 +135,7 @@ def main():
         ws = api.workspace(n, d, prec, dev)
         ll = ctypes.c_double()
         gp = (ctypes.c_double * 6)()
-        stage = (ctypes.c_float * 12)()
+        stage = (ctypes.c_float * len(STAGES))()
 
         def call():
             st = L.hawkes_grad(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), pc, ws.data_ptr(), ws.numel(),
@@ -151,7 +150,7 @@ def main():
             call()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        acc = np.zeros(12)
+        acc = np.zeros(len(STAGES))
         for _ in range(stage_steps if "+cull" not in prec else 0):
             st = L.hawkes_grad_timed(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), pc, ws.data_ptr(),
                                      ws.numel(), stream, ctypes.byref(ll), gx.data_ptr(), gp, stage)
@@ -227,7 +226,7 @@ def main():
            "path_roofline_frac": round(path_work / sec_mixed / peak, 4),
            "stage_ms": {k: round(float(v), 4) for k, v in zip(STAGES, stage_ms)},
            "stage_ms_note": "stages timed in sequence on one stream (hawkes_grad_timed); ms_per_step is "
-                            "hawkes_grad, where flaglist..final2 and fix2b/fix2a overlap pass2 on a side stream",
+                            "hawkes_grad, where fix1, final1 and fix2 overlap pass2 on a side stream",
            "fp64": fp64,
            "exact_culling": culling,
            "speedup_mixed_vs_fp64": (value / fp64["value"]) if fp64 else None,

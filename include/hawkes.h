@@ -108,17 +108,17 @@ int hawkes_grad_async(const double* x, const double* t, int64_t n, int d, const 
                       int prec, void* ws, size_t ws_bytes, void* stream, double* out8 /* device */,
                       double* grad_x /* device or NULL */);
 
-/* hawkes_grad plus per-stage device durations: stage_ms (host, 12 floats)
+/* hawkes_grad plus per-stage device durations: stage_ms (host, 9 floats)
  * receives the milliseconds between HIP events recorded on the call's stream
  * before and after each kernel; every stage runs in order on that stream
- * (no side stream), in launch order: prep, pack, pass1 (rates),
- * reduce1, flag list, fix-up 1, finalize, finalize reduction, pass2
- * (gradient), fix-up 2b, fix-up 2a, reduce2.  Used by the benchmark to price
+ * (no side stream), in launch order: prep, pack, pass1 (rates), reduce1,
+ * fix-up 1 (with the flagged-row list), finalize, pass2 (gradient), fix-up 2
+ * (with the finalize reduction), reduce2.  Used by the benchmark to price
  * each kernel against its roofline; the numerical results equal hawkes_grad's. */
 int hawkes_grad_timed(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p /* host */,
                       int prec, void* ws, size_t ws_bytes, void* stream,
                       double* loglik /* host or NULL */, double* grad_x /* device */,
-                      double* grad_params /* host or NULL */, float* stage_ms /* host, 12 */);
+                      double* grad_params /* host or NULL */, float* stage_ms /* host, 9 */);
 
 /* Per-event terms of the rate pass (Sec. 2.1) and the branching probability
  * used to colour events in the influenza application (Sec. 4.3): the

@@ -21,9 +21,8 @@ namespace hawkes {
 constexpr double kShiftMixed = 120.0;       // base-2 shift of the mixed pass's terms
 constexpr double kFloorMixed = -60.0;       // flag when lambda * 2^S < cmax * 2^-60
 constexpr double kFloorFp64 = -900.0;       // flag when lambda < cmax * 2^-900
-constexpr int kFixGrid = 256;
 constexpr int kTargetItems = 5120;
-constexpr int kNumStages = 12;
+constexpr int kNumStages = 9;
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -234,7 +233,7 @@ static inline void mark(hipStream_t s, int stage) {
 }
 
 // A side stream and two events.  In a gradient call the fix-up and finalize
-// kernels (flag list, fix1, final1, final2, fix2b, fix2a) run on the side
+// kernels (fix1, final1, fix2) run on the side
 // stream while pass 2 runs on the caller's stream: pass 2 reads nothing they
 // write, and k_reduce2, which reads both, waits for the side chain.
 struct Fork {
@@ -316,33 +315,30 @@ static bool launch_phases(const ReqDesc* reqs, int nreq, const BatchGrid& g, boo
     ok = ok && hipStreamWaitEvent(fk->side, fk->ready, 0) == hipSuccess;
     a = fk->side;
   }
-  k_flaglist<<<nreq, 1024, 0, a>>>(reqs);
-  mark(a, 5);
   k_fix1<D><<<dim3(kFixGrid, nreq), 256, 0, a>>>(reqs);
-  mark(a, 6);
+  mark(a, 5);
   k_final1<D, MIX><<<g.ev_blocks, kEvBlock, 0, a>>>(reqs, nreq);
-  mark(a, 7);
-  k_final2<<<nreq, 256, 0, a>>>(reqs);
-  mark(a, 8);
-  if (!grad) return ok;
+  mark(a, 6);
+  if (!grad) {
+    mark(a, 7);
+    k_fix2<D><<<nreq, kEvBlock, 0, a>>>(reqs, nreq, 0);   // the finalize reduction alone
+    mark(a, 8);
+    return ok;
+  }
+  // finalize reduction + both gradient fix-up sweeps
+  const int fix2_blocks = nreq + g.ev_blocks + kFixGrid * nreq;
   if (fork) {
-    k_fix2b<D><<<g.ev_blocks, kEvBlock, 0, a>>>(reqs, nreq);
-    k_fix2a<D><<<dim3(kFixGrid, nreq), 256, 0, a>>>(reqs);
+    k_fix2<D><<<fix2_blocks, kEvBlock, 0, a>>>(reqs, nreq, g.ev_blocks);
     ok = ok && hipEventRecord(fk->done, a) == hipSuccess;
   }
   if constexpr (MIX) k_pass2_mixed<D><<<g.items, kThreads, 0, s>>>(reqs, nreq);
   else k_pass2<D, MIX><<<g.items, kThreads, 0, s>>>(reqs, nreq);
-  mark(s, 9);
-  if (fork) {
-    ok = ok && hipStreamWaitEvent(s, fk->done, 0) == hipSuccess;
-  } else {
-    k_fix2b<D><<<g.ev_blocks, kEvBlock, 0, s>>>(reqs, nreq);
-    mark(s, 10);
-    k_fix2a<D><<<dim3(kFixGrid, nreq), 256, 0, s>>>(reqs);
-    mark(s, 11);
-  }
+  mark(s, 7);
+  if (fork) ok = ok && hipStreamWaitEvent(s, fk->done, 0) == hipSuccess;
+  else k_fix2<D><<<fix2_blocks, kEvBlock, 0, s>>>(reqs, nreq, g.ev_blocks);
+  mark(s, 8);
   k_reduce2<D, MIX><<<g.ev_blocks, kRedThreads, 0, s>>>(reqs, nreq);
-  mark(s, 12);
+  mark(s, 9);
   return ok;
 }
 

@@ -31,6 +31,7 @@ constexpr int kRowsPerLane = HK_ROWS_PER_LANE;  // rows each lane owns in the pa
 constexpr int kBandRows = kThreads * kRowsPerLane;  // rows per band (512)
 constexpr int kTile = 64;               // columns per tile (one wave width)
 constexpr int kMaxD = 8;
+constexpr int kFixGrid = 256;            // workgroups per request in the fix-up kernels
 constexpr int kFixSeg = 16;             // partner segments per flagged row in the fix-up kernels
 constexpr int kEvBlock = 256;           // events per block of the per-event kernels
 // float32 pair passes: steps whose exps are issued together (rate, gradient)

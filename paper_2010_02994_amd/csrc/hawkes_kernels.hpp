@@ -16,7 +16,7 @@
 // exponent is formed in base 2 with a constant shift S (terms carry a factor
 // 2^S), exp is v_exp_f32, and per-tile float32 partials fold into float64.
 // Rows whose rate sits below the shifted window are recomputed in float64 by
-// the fix-up kernels (k_fix1, k_fix2a/b), so no event loses range.
+// the fix-up kernels (k_fix1, k_fix2), so no event loses range.
 #pragma once
 #include <type_traits>
 
@@ -931,7 +931,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H
 // combined by two butterfly steps, which gives every lane the same value; the
 // four lanes of an event always branch together), so the kernel keeps enough
 // loads in flight to stream the partial buffers.
-// Flagged rows of each block are staged in index order for k_flaglist.
+// Flagged rows of each block are staged in index order for k_fix1.
 constexpr int kRedThreads = 4 * kEvBlock;
 
 __device__ __forceinline__ double quad_sum(double v) {
@@ -1026,56 +1026,66 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce1(const ReqDesc* __restri
   }
 }
 
-// Ordered list of the flagged rows of each request (one workgroup of 1024
-// threads per request): scan of the per-block counts, then copy the staged rows.
-__global__ void __launch_bounds__(1024) k_flaglist(const ReqDesc* __restrict__ reqs) {
-  __shared__ int s_scan[1024];
-  const ReqDesc& rq = reqs[blockIdx.x];
-  if (glb(rq.status)[kStData] != 0) return;
-  const int nblk = rq.kp.nblk, tid = threadIdx.x;
-  const int per = (nblk + 1023) / 1024;
-  const int lo = min(nblk, tid * per), hi = min(nblk, lo + per);
-  int cnt = 0;
-  for (int b = lo; b < hi; ++b) cnt += glb(rq.bcount)[b];
-  s_scan[tid] = cnt;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int v = tid >= off ? s_scan[tid - off] : 0;
-    __syncthreads();
-    s_scan[tid] += v;
-    __syncthreads();
-  }
-  int pos = s_scan[tid] - cnt;
-  for (int b = lo; b < hi; ++b) {
-    const int c = glb(rq.bcount)[b];
-    for (int k = 0; k < c; ++k) {
-      const int i = glb(rq.bstage)[(int64_t)b * kEvBlock + k];
-      glb(rq.list)[pos] = i;
-      glb(rq.listpos)[i] = pos;
-      ++pos;
-    }
-  }
-  if (tid == 1023) glb(rq.status)[kStFlagCount] = s_scan[1023];
-}
-
 // Exact float64 recomputation of the six row sums of each flagged row.  The
 // partners are split into kFixSeg segments; each (row, segment) task finds the
 // segment's largest log pair term m_s, then sums exp(term - m_s) -- no term that
 // matters can underflow.  k_final1 merges the segments in a fixed order.
 // fixpart[(f * kFixSeg + s) * 8 + q]: q < 6 the unweighted sums times exp(-m_s), q = 6 m_s.
+// The ordered list of flagged rows comes from k_reduce1's per-block counts
+// and staged rows: every workgroup scans the counts (256 threads, each over a
+// chunk of consecutive blocks) and finds its tasks' rows from the scan;
+// workgroup 0 of each request also writes the list, each row's list position
+// and the count, which the kernels after this one read.
 template <int D>
 __global__ void __launch_bounds__(256) k_fix1(const ReqDesc* __restrict__ reqs) {
   __shared__ double sh[256];
+  __shared__ int s_scan[256];
   const ReqDesc& rq = reqs[blockIdx.y];
-  if (glb(rq.status)[kStData] != 0) return;
+  if (uni(glb(rq.status)[kStData]) != 0) return;
   const KParams& kp = rq.kp;
+  const int tid = threadIdx.x;
+  const int per = (kp.nblk + 255) / 256;
+  const int lo = min(kp.nblk, tid * per), hi = min(kp.nblk, lo + per);
+  int own = 0;
+  for (int b = lo; b < hi; ++b) own += glb(rq.bcount)[b];
+  s_scan[tid] = own;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = tid >= off ? s_scan[tid - off] : 0;
+    __syncthreads();
+    s_scan[tid] += v;
+    __syncthreads();
+  }
+  const int cnt = s_scan[255];
+  if (blockIdx.x == 0) {
+    int pos = s_scan[tid] - own;
+    for (int b = lo; b < hi; ++b) {
+      const int c = glb(rq.bcount)[b];
+      for (int k = 0; k < c; ++k) {
+        const int i = glb(rq.bstage)[(int64_t)b * kEvBlock + k];
+        glb(rq.list)[pos] = i;
+        glb(rq.listpos)[i] = pos;
+        ++pos;
+      }
+    }
+    if (tid == 0) glb(rq.status)[kStFlagCount] = cnt;
+  }
   const auto x = glb(rq.x);
   const auto t = glb(rq.t);
-  const int cnt = glb(rq.status)[kStFlagCount];
   const int seg = (kp.n + kFixSeg - 1) / kFixSeg;
   for (int task = blockIdx.x; task < cnt * kFixSeg; task += gridDim.x) {
     const int f = task / kFixSeg, sg = task % kFixSeg;
-    const int i = glb(rq.list)[f];
+    // row f of the list: the first chunk whose inclusive count exceeds f,
+    // then the block inside it
+    int c0 = 0, c1 = 255;
+    while (c0 < c1) {
+      const int mid = (c0 + c1) >> 1;
+      if (s_scan[mid] > f) c1 = mid; else c0 = mid + 1;
+    }
+    int r = f - (c0 > 0 ? s_scan[c0 - 1] : 0);
+    int b = c0 * per;
+    for (int cb = glb(rq.bcount)[b]; r >= cb; cb = glb(rq.bcount)[b]) { r -= cb; ++b; }
+    const int i = glb(rq.bstage)[(int64_t)b * kEvBlock + r];
     const int j0 = sg * seg, j1 = min(kp.n, j0 + seg);
     double xi[D];
 #pragma unroll
@@ -1198,10 +1208,8 @@ __global__ void __launch_bounds__(kEvBlock) k_final1(const ReqDesc* __restrict__
 }
 
 // Sum the per-block partials in block order (one workgroup per request);
-// out8 = [ell, 6 gradients, status].
-__global__ void __launch_bounds__(256) k_final2(const ReqDesc* __restrict__ reqs) {
-  __shared__ double sh[256];
-  const ReqDesc& rq = reqs[blockIdx.x];
+// out8 = [ell, 6 gradients, status].  Runs as the first blocks of k_fix2.
+__device__ __forceinline__ void final2_block(const ReqDesc& rq, double* sh) {
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int bad = glb(rq.status)[kStData];
   if (bad == 0) {
@@ -1233,12 +1241,12 @@ __global__ void __launch_bounds__(256) k_final2(const ReqDesc* __restrict__ reqs
 // formed as exp(log-term - log lambda_j) in float64.
 // Sweep B (one thread per event i): sum over flagged j of c (x_j - x_i).
 template <int D>
-__global__ void __launch_bounds__(kEvBlock) k_fix2b(const ReqDesc* __restrict__ reqs, int nreq) {
-  const int rid = find_req(reqs, nreq, blockIdx.x, 1);
+__device__ __forceinline__ void fix2b_block(const ReqDesc* __restrict__ reqs, int nreq, int blk) {
+  const int rid = find_req(reqs, nreq, blk, 1);
   const ReqDesc& rq = reqs[rid];
   const KParams& kp = rq.kp;
-  const int i = (blockIdx.x - rq.blk_ev) * kEvBlock + threadIdx.x;
-  if (i >= kp.n || glb(rq.status)[kStData] != 0 || glb(rq.status)[kStZero] != 0) return;
+  const int i = (blk - rq.blk_ev) * kEvBlock + threadIdx.x;
+  if (i >= kp.n || glb(rq.status)[kStData] != 0) return;
   const auto x = glb(rq.x);
   const auto t = glb(rq.t);
   const int cnt = glb(rq.status)[kStFlagCount];
@@ -1254,6 +1262,7 @@ __global__ void __launch_bounds__(kEvBlock) k_fix2b(const ReqDesc* __restrict__ 
     for (int q = 0; q < D; ++q) { dx[q] = x[(int64_t)j * D + q] - xi[q]; r2 += dx[q] * dx[q]; }
     const double dt = t[j] - ti;   // > 0 when j is the later event
     const double Lj = glb(rq.logl)[j];
+    if (Lj == -INFINITY) continue;   // lambda_j = 0: the call reports a zero rate
     double c = 0.0;
     if (dt != 0.0) c += exp(kp.log_cbg - kp.alpha * r2 - kp.beta * dt * dt - Lj) * kp.itx2;
     if (dt > 0.0) c += exp(kp.log_cse - kp.omega * dt - kp.gamma * r2 - Lj) * kp.ih2;
@@ -1267,16 +1276,14 @@ __global__ void __launch_bounds__(kEvBlock) k_fix2b(const ReqDesc* __restrict__ 
 // Sweep A (tasks = flagged row x partner segment): partial sums over the
 // segment's events i of c (x_i - x_j) for flagged row j, merged by k_reduce2.
 template <int D>
-__global__ void __launch_bounds__(256) k_fix2a(const ReqDesc* __restrict__ reqs) {
-  __shared__ double sh[256];
-  const ReqDesc& rq = reqs[blockIdx.y];
-  if (uni(glb(rq.status)[kStData]) != 0 || uni(glb(rq.status)[kStZero]) != 0) return;
+__device__ __forceinline__ void fix2a_block(const ReqDesc& rq, int bx, int nbx, double* sh) {
+  if (uni(glb(rq.status)[kStData]) != 0) return;
   const KParams& kp = rq.kp;
   const auto x = glb(rq.x);
   const auto t = glb(rq.t);
   const int cnt = glb(rq.status)[kStFlagCount];
   const int seg = (kp.n + kFixSeg - 1) / kFixSeg;
-  for (int task = blockIdx.x; task < cnt * kFixSeg; task += gridDim.x) {
+  for (int task = bx; task < cnt * kFixSeg; task += nbx) {
     const int f = task / kFixSeg, sg = task % kFixSeg;
     const int j = glb(rq.list)[f];
     const int i0 = sg * seg, i1 = min(kp.n, i0 + seg);
@@ -1284,6 +1291,7 @@ __global__ void __launch_bounds__(256) k_fix2a(const ReqDesc* __restrict__ reqs)
 #pragma unroll
     for (int q = 0; q < D; ++q) xj[q] = x[(int64_t)j * D + q];
     const double tj = t[j], Lj = glb(rq.logl)[j];
+    if (Lj == -INFINITY) continue;   // lambda_j = 0: the call reports a zero rate
     double g[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) g[q] = 0.0;
@@ -1305,6 +1313,28 @@ __global__ void __launch_bounds__(256) k_fix2a(const ReqDesc* __restrict__ reqs)
       if (threadIdx.x == 0) glb(rq.fixpart)[((int64_t)f * kFixSeg + sg) * 8 + q] = v;
     }
   }
+}
+
+// The finalize reduction and both gradient fix-up sweeps in one launch
+// (none reads what another writes): blocks [0, nreq) reduce each request's
+// finalize partials, the next ev_blocks take sweep B, and kFixGrid blocks
+// per request take sweep A.
+template <int D>
+__global__ void __launch_bounds__(kEvBlock) k_fix2(const ReqDesc* __restrict__ reqs, int nreq, int ev_blocks) {
+  static_assert(kEvBlock == 256, "the finalize reduction uses 256 threads");
+  __shared__ double sh[kEvBlock];
+  int b = blockIdx.x;
+  if (b < nreq) {
+    final2_block(reqs[b], sh);
+    return;
+  }
+  b -= nreq;
+  if (b < ev_blocks) {
+    fix2b_block<D>(reqs, nreq, b);
+    return;
+  }
+  b -= ev_blocks;
+  fix2a_block<D>(reqs[b / kFixGrid], b % kFixGrid, kFixGrid, sh);
 }
 
 // grad_x = row partials + column partials + fix-up terms (fixed order; four
