@@ -94,18 +94,6 @@ __device__ __forceinline__ void wave_totals_lane63(R* v) {
   for (int k = 0; k < K; ++k) v[k] += dpp_step<0x143, 0xf>(v[k]);  // row_bcast:31
 }
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
 // erfc(w) for w >= 0 in float32: the Chebyshev-fitted form
 // t exp(-w^2 + P(t)), t = 1/(1 + w/2), of Press et al., Numerical Recipes
 // (2nd ed., Sec. 6.2, "erfcc"), relative error below 1.2e-7 for all w >= 0,
@@ -156,7 +144,7 @@ __global__ void __launch_bounds__(kThreads) k_bmds_tiles(Args a) {
   using R = typename std::conditional<MIX, float, double>::type;
   __shared__ R s_x[kTR][D];
   __shared__ R s_row[kThreads / 64][kTR][D];
-  __shared__ double sh[kThreads];
+  __shared__ double sh[4 * kThreads];
   const int64_t tile = blockIdx.x;
   int lo = 0, hi = a.nb - 1;   // band: largest I with band_offset(I) <= tile
   while (lo < hi) {
@@ -246,30 +234,23 @@ __global__ void __launch_bounds__(kThreads) k_bmds_tiles(Args a) {
   }
 #pragma unroll
   for (int q = 0; q < D; ++q) a.pcol[(tile * kTC + threadIdx.x) * D + q] = (double)g[q];
-  const double t0 = block_sum((double)tsum, sh);
-  const double t1 = block_sum((double)dsum, sh);
-  const double t2 = block_sum((double)cnt, sh);
-  const double t3 = block_sum((double)bad, sh);
-  if (threadIdx.x == 0) {
-    a.ptile[tile * 4 + 0] = t0;
-    a.ptile[tile * 4 + 1] = t1;
-    a.ptile[tile * 4 + 2] = t2;
-    a.ptile[tile * 4 + 3] = t3;
-  }
+  double tot[4] = {(double)tsum, (double)dsum, (double)cnt, (double)bad};
+  block_sum_n(tot, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) a.ptile[tile * 4 + k] = tot[k];
 }
 
 // One workgroup: the tile totals in tile order, the -M/2 log sigma^2 and
 // -M/sigma terms, and the data checks (invalid deltas, non-finite x).
 __global__ void __launch_bounds__(kFinalThreads) k_bmds_final(Args a, int D) {
-  __shared__ double sh[kFinalThreads];
-  double v[4] = {0, 0, 0, 0};
+  __shared__ double sh[5 * kFinalThreads];
+  double v[5] = {0, 0, 0, 0, 0};   // four tile totals, then the non-finite coordinates
   for (int64_t t = threadIdx.x; t < a.ntiles; t += kFinalThreads)
     for (int k = 0; k < 4; ++k) v[k] += a.ptile[t * 4 + k];
-  double nonfinite = 0.0;
   for (int64_t e = threadIdx.x; e < (int64_t)a.n * D; e += kFinalThreads)
-    if (!isfinite(a.x[e])) nonfinite += 1.0;
-  for (int k = 0; k < 4; ++k) v[k] = block_sum(v[k], sh);
-  nonfinite = block_sum(nonfinite, sh);
+    if (!isfinite(a.x[e])) v[4] += 1.0;
+  block_sum_n(v, sh);
+  const double nonfinite = v[4];
   if (threadIdx.x == 0) {
     const double M = v[2];
     const bool bad = v[3] > 0.0 || nonfinite > 0.0;

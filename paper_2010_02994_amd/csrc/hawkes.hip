@@ -290,12 +290,15 @@ static ForkPool& fork_pool() {
 // The phases over every request of a batch (all with the same D and
 // precision).  reqs: device array of descriptors; totals: grid sizes.
 // fk == nullptr: everything in order on s (used when stages are timed).
+// one != nullptr: a single request whose descriptor the first kernel writes
+// to reqs[0].
 template <int D, bool MIX>
 static bool launch_phases(const ReqDesc* reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s,
-                          const Fork* fk) {
+                          const Fork* fk, const ReqDesc* one) {
   bool ok = true;
   mark(s, 0);
-  k_init<D><<<nreq, 1024, 0, s>>>(reqs);
+  if (one) k_init_one<D><<<1, 1024, 0, s>>>(*one, const_cast<ReqDesc*>(reqs));
+  else k_init<D><<<nreq, 1024, 0, s>>>(reqs);
   mark(s, 1);
   k_pack<D, MIX><<<g.pad_blocks, kEvBlock, 0, s>>>(reqs, nreq);
   mark(s, 2);
@@ -344,25 +347,27 @@ static bool launch_phases(const ReqDesc* reqs, int nreq, const BatchGrid& g, boo
 
 template <bool MIX>
 static bool dispatch_d(int d, const ReqDesc* reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s,
-                       const Fork* fk) {
+                       const Fork* fk, const ReqDesc* one) {
   switch (d) {
-    case 1: return launch_phases<1, MIX>(reqs, nreq, g, grad, s, fk);
-    case 2: return launch_phases<2, MIX>(reqs, nreq, g, grad, s, fk);
-    case 3: return launch_phases<3, MIX>(reqs, nreq, g, grad, s, fk);
-    case 4: return launch_phases<4, MIX>(reqs, nreq, g, grad, s, fk);
-    case 5: return launch_phases<5, MIX>(reqs, nreq, g, grad, s, fk);
-    case 6: return launch_phases<6, MIX>(reqs, nreq, g, grad, s, fk);
-    case 7: return launch_phases<7, MIX>(reqs, nreq, g, grad, s, fk);
-    case 8: return launch_phases<8, MIX>(reqs, nreq, g, grad, s, fk);
+    case 1: return launch_phases<1, MIX>(reqs, nreq, g, grad, s, fk, one);
+    case 2: return launch_phases<2, MIX>(reqs, nreq, g, grad, s, fk, one);
+    case 3: return launch_phases<3, MIX>(reqs, nreq, g, grad, s, fk, one);
+    case 4: return launch_phases<4, MIX>(reqs, nreq, g, grad, s, fk, one);
+    case 5: return launch_phases<5, MIX>(reqs, nreq, g, grad, s, fk, one);
+    case 6: return launch_phases<6, MIX>(reqs, nreq, g, grad, s, fk, one);
+    case 7: return launch_phases<7, MIX>(reqs, nreq, g, grad, s, fk, one);
+    case 8: return launch_phases<8, MIX>(reqs, nreq, g, grad, s, fk, one);
   }
   return false;
 }
 
 // Enqueue a batch whose descriptors already sit in device memory (block
-// offsets filled in).  Gradient batches fork onto a side stream unless the
-// stages are being timed.  Returns HAWKES_EDEVICE if a launch failed.
+// offsets filled in), or, with one != nullptr, a single request whose
+// descriptor the first kernel copies to dev_reqs[0].  Gradient batches fork
+// onto a side stream unless the stages are being timed.  Returns
+// HAWKES_EDEVICE if a launch failed.
 int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const BatchGrid& g, bool grad,
-                 hipStream_t s) {
+                 hipStream_t s, const ReqDesc* one) {
   (void)hipGetLastError();
   int dev = -1;
   Fork* fk = nullptr;
@@ -371,8 +376,8 @@ int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const Batc
     const bool capturing = hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
     fk = fork_pool().take(dev, !capturing);
   }
-  const bool ok = mixed ? dispatch_d<true>(d, dev_reqs, nreq, g, grad, s, fk)
-                        : dispatch_d<false>(d, dev_reqs, nreq, g, grad, s, fk);
+  const bool ok = mixed ? dispatch_d<true>(d, dev_reqs, nreq, g, grad, s, fk, one)
+                        : dispatch_d<false>(d, dev_reqs, nreq, g, grad, s, fk, one);
   if (fk) fork_pool().give(dev, fk);
   return ok && hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
 }
@@ -413,10 +418,7 @@ int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_p
   desc.terms = terms;
   const BatchGrid g = assign_blocks(&desc, 1);
   ReqDesc* dev = at<ReqDesc>(ws, Lo.off_desc);
-  (void)hipGetLastError();
-  k_setdesc<<<1, 64, 0, s>>>(desc, dev);
-  if (hipGetLastError() != hipSuccess) return HAWKES_EDEVICE;
-  return launch_batch(d, Lo.mixed, dev, 1, g, grad_x != nullptr, s);
+  return launch_batch(d, Lo.mixed, dev, 1, g, grad_x != nullptr, s, &desc);
 }
 
 static int run_sync(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,

@@ -43,6 +43,27 @@ constexpr int kGradExpSteps = HK_GRAD_EXP_STEPS;
 struct IPair { int x, y; };
 struct alignas(16) Chunk16 { unsigned a, b, c, d; };
 
+// Sums NV values over the workgroup (blockDim.x a power of two; sh holds
+// NV * blockDim.x elements) with one fixed-shape tree per value, so the
+// result does not depend on timing; every thread receives the totals.
+template <typename T, int NV>
+__device__ __forceinline__ void block_sum_n(T (&v)[NV], T* sh) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) sh[q * nt + tid] = v[q];
+  __syncthreads();
+  for (int s = nt / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) sh[q * nt + tid] += sh[q * nt + tid + s];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = sh[q * nt];
+  __syncthreads();
+}
+
 // Status words kept in each request's workspace.
 enum StatusSlot { kStData = 0, kStZero = 1, kStFlagCount = 2, kStSlots = 16 };
 

@@ -32,7 +32,8 @@ KParams make_kparams(const Layout& Lo, const hawkes_params_t* p);
 ReqDesc make_desc(const Layout& Lo, const KParams& kp, const double* x, const double* t, void* ws, double* out8,
                   double* grad_x);
 BatchGrid assign_blocks(ReqDesc* descs, int nreq);
-int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s);
+int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const BatchGrid& g, bool grad, hipStream_t s,
+                 const ReqDesc* one = nullptr);
 // Enqueue one full evaluation (validation, rate pass, finalize and, when
 // grad_x is not null, the gradient pass) with no host synchronization.
 int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,

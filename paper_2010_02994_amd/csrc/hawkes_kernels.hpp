@@ -43,21 +43,6 @@ template <int D> struct Traits<D, false> {
 __device__ __forceinline__ float exp_pair(float z) { return __builtin_amdgcn_exp2f(z); }
 __device__ __forceinline__ double exp_pair(double z) { return exp(z); }
 
-template <typename T>
-__device__ __forceinline__ T block_sum_256(T v, T* sh) {
-  // fixed-shape tree over 256 threads (deterministic)
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) sh[tid] += sh[tid + s];
-    __syncthreads();
-  }
-  T r = sh[0];
-  __syncthreads();
-  return r;
-}
-
 __device__ __forceinline__ double block_max_256(double v, double* sh) {
   const int tid = threadIdx.x;
   sh[tid] = v;
@@ -118,8 +103,7 @@ __device__ __forceinline__ int find_req(const ReqDesc* __restrict__ reqs, int nr
 // table of the pair passes.  Items run band-major from the last (longest)
 // band to the first.  Data validation happens in k_pack.
 template <int D>
-__global__ void __launch_bounds__(1024) k_init(const ReqDesc* __restrict__ reqs) {
-  const ReqDesc& rq = reqs[blockIdx.x];
+__device__ __forceinline__ void init_block(const ReqDesc& rq) {
   const auto x = glb(rq.x);
   const auto t = glb(rq.t);
   const int n = rq.kp.n, nb = rq.kp.nb, L = rq.kp.L;
@@ -166,6 +150,19 @@ __global__ void __launch_bounds__(1024) k_init(const ReqDesc* __restrict__ reqs)
       base += ch;
     }
   }
+}
+
+template <int D>
+__global__ void __launch_bounds__(1024) k_init(const ReqDesc* __restrict__ reqs) {
+  init_block<D>(reqs[blockIdx.x]);
+}
+
+// Single-request form: the descriptor arrives as a kernel argument, is
+// written to device memory for the later kernels, and drives the set-up.
+template <int D>
+__global__ void __launch_bounds__(1024) k_init_one(ReqDesc d, ReqDesc* __restrict__ dst) {
+  if (threadIdx.x == 0) *dst = d;
+  init_block<D>(d);
 }
 
 // Packed records and tie groups.  first[i] is the first index with t == t[i]
@@ -825,7 +822,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H
   constexpr int NQ = D;
   __shared__ Rec s_rec[2][2 * kTile];
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
-  __shared__ double s_red[kThreads];
+  __shared__ double s_red[2 * kThreads];
   const int rid = find_req(reqs, nreq, blockIdx.x, 0);
   const ReqDesc& rq = reqs[rid];
   if (uni(glb(rq.status)[kStData]) != 0) return;
@@ -911,11 +908,11 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H
       glb(static_cast<float*>(rq.prow))[((int64_t)item * D + q) * kBandRows + lr] = (float)S.acc[r][q];
   }
   // the item's two moment sums, fixed-order over the workgroup
-  const double m0 = block_sum_256(S.momd[0], s_red);
-  const double m1 = block_sum_256(S.momd[1], s_red);
+  double mom[2] = {S.momd[0], S.momd[1]};
+  block_sum_n(mom, s_red);
   if (threadIdx.x == 0) {
-    glb(rq.mompart)[(int64_t)item * 2 + 0] = m0;
-    glb(rq.mompart)[(int64_t)item * 2 + 1] = m1;
+    glb(rq.mompart)[(int64_t)item * 2 + 0] = mom[0];
+    glb(rq.mompart)[(int64_t)item * 2 + 1] = mom[1];
   }
 }
 
@@ -1038,7 +1035,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce1(const ReqDesc* __restri
 // and the count, which the kernels after this one read.
 template <int D>
 __global__ void __launch_bounds__(256) k_fix1(const ReqDesc* __restrict__ reqs) {
-  __shared__ double sh[256];
+  __shared__ double sh[6 * 256];
   __shared__ int s_scan[256];
   const ReqDesc& rq = reqs[blockIdx.y];
   if (uni(glb(rq.status)[kStData]) != 0) return;
@@ -1119,12 +1116,12 @@ __global__ void __launch_bounds__(256) k_fix1(const ReqDesc* __restrict__ reqs) 
         a[3] += e; a[4] += e * r2; a[5] += e * dt;
       }
     }
+    block_sum_n(a, sh);
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const double v = block_sum_256(a[q], sh);
-      if (threadIdx.x == 0) glb(rq.fixpart)[((int64_t)f * kFixSeg + sg) * 8 + q] = v;
+      for (int q = 0; q < 6; ++q) glb(rq.fixpart)[((int64_t)f * kFixSeg + sg) * 8 + q] = a[q];
+      glb(rq.fixpart)[((int64_t)f * kFixSeg + sg) * 8 + 6] = m;
     }
-    if (threadIdx.x == 0) glb(rq.fixpart)[((int64_t)f * kFixSeg + sg) * 8 + 6] = m;
   }
 }
 
@@ -1135,7 +1132,7 @@ __device__ __forceinline__ double std_normal_pdf(double z) { return 0.3989422804
 // parameter-gradient terms; per-block fixed-order partials.
 template <int D, bool MIX>
 __global__ void __launch_bounds__(kEvBlock) k_final1(const ReqDesc* __restrict__ reqs, int nreq) {
-  __shared__ double sh[kEvBlock];
+  __shared__ double sh[8 * kEvBlock];
   const int rid = find_req(reqs, nreq, blockIdx.x, 1);
   const ReqDesc& rq = reqs[rid];
   if (glb(rq.status)[kStData] != 0) return;
@@ -1200,11 +1197,10 @@ __global__ void __launch_bounds__(kEvBlock) k_final1(const ReqDesc* __restrict__
       tp[3] = kp.cse * s[3] * il;
     }
   }
+  block_sum_n(v, sh);
+  if (threadIdx.x == 0)
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const double r = block_sum_256(v[q], sh);
-    if (threadIdx.x == 0) glb(rq.bpart)[(int64_t)lb * 8 + q] = r;
-  }
+    for (int q = 0; q < 8; ++q) glb(rq.bpart)[(int64_t)lb * 8 + q] = v[q];
 }
 
 // Sum the per-block partials in block order (one workgroup per request);
@@ -1217,8 +1213,7 @@ __device__ __forceinline__ void final2_block(const ReqDesc& rq, double* sh) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) v[q] += glb(rq.bpart)[(int64_t)b * 8 + q];
   }
-#pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = block_sum_256(v[q], sh);
+  block_sum_n(v, sh);
   if (threadIdx.x == 0) {
     const auto out8 = glb(rq.out8);
     if (bad != 0) {
@@ -1307,11 +1302,10 @@ __device__ __forceinline__ void fix2a_block(const ReqDesc& rq, int bx, int nbx, 
 #pragma unroll
       for (int q = 0; q < D; ++q) g[q] += c * dx[q];
     }
+    block_sum_n(g, sh);
+    if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-      const double v = block_sum_256(g[q], sh);
-      if (threadIdx.x == 0) glb(rq.fixpart)[((int64_t)f * kFixSeg + sg) * 8 + q] = v;
-    }
+      for (int q = 0; q < D; ++q) glb(rq.fixpart)[((int64_t)f * kFixSeg + sg) * 8 + q] = g[q];
   }
 }
 
@@ -1322,7 +1316,7 @@ __device__ __forceinline__ void fix2a_block(const ReqDesc& rq, int bx, int nbx, 
 template <int D>
 __global__ void __launch_bounds__(kEvBlock) k_fix2(const ReqDesc* __restrict__ reqs, int nreq, int ev_blocks) {
   static_assert(kEvBlock == 256, "the finalize reduction uses 256 threads");
-  __shared__ double sh[kEvBlock];
+  __shared__ double sh[8 * kEvBlock];
   int b = blockIdx.x;
   if (b < nreq) {
     final2_block(reqs[b], sh);
@@ -1422,10 +1416,5 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce2(const ReqDesc* __restri
   for (int q = 0; q < D; ++q) grad_x[(int64_t)i * D + q] = s[q];
 }
 
-// Writes one request descriptor into device memory (the single-call entry
-// points; batched launches copy their descriptor arrays instead).
-__global__ void k_setdesc(ReqDesc d, ReqDesc* __restrict__ dst) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = d;
-}
 
 }  // namespace hawkes

@@ -233,7 +233,7 @@ __device__ __forceinline__ int segs_for(int cnt, int n) {
 // proposed place; a moved row sits at its proposed location.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_mwg_exact(Step s) {
-  __shared__ double sh[kBlock];
+  __shared__ double sh[2 * kBlock];
   const int cnt = s.state[1];
   const int segs = segs_for(cnt, s.n);
   const int seg = (s.n + segs - 1) / segs;
@@ -258,11 +258,11 @@ __global__ void __launch_bounds__(kBlock) k_mwg_exact(Step s) {
       a += pa;
       b += pb;
     }
-    a = block_sum(a, sh);
-    b = block_sum(b, sh);
+    double ab[2] = {a, b};
+    block_sum_n(ab, sh);
     if (threadIdx.x == 0) {
-      s.part[((int64_t)e * segs + sg) * 2 + 0] = a;
-      s.part[((int64_t)e * segs + sg) * 2 + 1] = b;
+      s.part[((int64_t)e * segs + sg) * 2 + 0] = ab[0];
+      s.part[((int64_t)e * segs + sg) * 2 + 1] = ab[1];
     }
   }
 }
@@ -348,7 +348,7 @@ __global__ void __launch_bounds__(kBlock) k_mwg_apply(Step s) {
 // with C_i the background's time integral and E_i = 1 - exp(-omega (T - t_i)).
 __global__ void __launch_bounds__(kListThreads) k_reweight(const double* t, int n, Model m, double tau_t,
                                                              const double* terms, double* out3) {
-  __shared__ double sh[kListThreads];
+  __shared__ double sh[3 * kListThreads];
   const double T = t[n - 1];
   double ll = 0.0, gm = 0.0, gt = 0.0;
   for (int i = threadIdx.x; i < n; i += kListThreads) {
@@ -362,14 +362,10 @@ __global__ void __launch_bounds__(kListThreads) k_reweight(const double* t, int 
     gm += a / lam - C;
     gt += b / lam - E;
   }
-  ll = block_sum(ll, sh);
-  gm = block_sum(gm, sh);
-  gt = block_sum(gt, sh);
-  if (threadIdx.x == 0) {
-    out3[0] = ll;
-    out3[1] = gm;
-    out3[2] = gt;
-  }
+  double v[3] = {ll, gm, gt};
+  block_sum_n(v, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) out3[k] = v[k];
 }
 
 static Model make_model(const hawkes_params_t* p, int d) {
