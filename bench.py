@@ -341,6 +341,49 @@ def leapfrog_bench(dev, trajectories: int):
                      "graph_ms_per_trajectory": elg * 1e3,
                      "status": float(out8[7].item()), "inside_cells": inside}
         del graph
+    out["flu_joint"] = flu_leapfrog_bench(dev, trajectories)
+    return out
+
+
+def flu_leapfrog_bench(dev, trajectories: int):
+    """The influenza model's HMC (N = 4,733 cases, D = 6, 64 countries): 20
+    unconstrained leapfrog steps whose every gradient is the Hawkes
+    log-likelihood gradient plus the Bayesian MDS gradient."""
+    import torch
+    from paper_2010_02994_amd import api, workloads
+    w, c = workloads.flu_case()
+    t = torch.tensor(w.t, device=dev)
+    dl = torch.tensor(c.delta, device=dev)
+    rng = np.random.default_rng(12)
+    steps, eps = 20, 0.001
+    out = {"workload": f"{w.name}: 20-step leapfrog on the Hawkes + MDS potential", "steps": steps, "eps": eps}
+    for prec in ("mixed", "fp64"):
+        x = torch.tensor(w.x, device=dev)
+        p = torch.tensor(rng.standard_normal(w.x.shape), device=dev)
+        g, out8, out4 = api.leapfrog_bmds(x, p, t, w.params, dl, c.sigma, eps, steps, prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(trajectories):
+            p.copy_(torch.tensor(rng.standard_normal(w.x.shape), device=dev))
+            g, out8, out4 = api.leapfrog_bmds(x, p, t, w.params, dl, c.sigma, eps, steps, prec=prec, grad_x=g,
+                                              have_grad=True, out8=out8, out4=out4)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / trajectories
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            api.leapfrog_bmds(x, p, t, w.params, dl, c.sigma, eps, steps, prec=prec, grad_x=g, have_grad=True,
+                              out8=out8, out4=out4)
+        graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(trajectories):
+            graph.replay()
+        torch.cuda.synchronize()
+        elg = (time.perf_counter() - t0) / trajectories
+        out[prec] = {"ms_per_trajectory": el * 1e3, "ms_per_step": el * 1e3 / steps,
+                     "graph_ms_per_trajectory": elg * 1e3, "hawkes_status": float(out8[7].item()),
+                     "mds_status": float(out4[3].item())}
+        del graph
     return out
 
 

@@ -234,6 +234,24 @@ size_t hawkes_bmds_workspace_bytes(int64_t n, int d);
 int hawkes_bmds(const double* x, const double* delta, int64_t n, int d, double sigma, int prec, void* ws,
                 size_t ws_bytes, void* stream, double* out4 /* device, 4 */, double* grad_x /* device or NULL */);
 
+/* Leapfrog trajectory for the influenza model (Sec. 3: HMC over the latent
+ * locations evaluates both the Hawkes likelihood and the MDS likelihood of
+ * eq. bmdsLikelihood, and both gradients, at every step): as hawkes_leapfrog
+ * with the potential -(ell_hawkes(x) + ell_mds(x)), so every gradient is the
+ * sum of hawkes_grad's and hawkes_bmds's location gradients (formed as the
+ * Hawkes gradient, then the MDS gradient added in place).  delta, sigma: as
+ * for hawkes_bmds; bws (device, hawkes_bmds_workspace_bytes(n, d) bytes) is
+ * the MDS workspace.  out8 receives the final Hawkes evaluation and out4
+ * (device, 4) the final MDS evaluation, both as from the single calls.  The
+ * MDS term runs at prec without HAWKES_CULL.  Host-side argument errors return
+ * at once; enqueue only. */
+int hawkes_leapfrog_bmds(double* x /* device, n*d */, double* p /* device, n*d */, const double* t, int64_t n, int d,
+                         const hawkes_params_t* prm /* host */, int prec, const double* delta /* device, n*n */,
+                         double sigma, double eps, int steps, int bound, const double* b0 /* device or NULL */,
+                         const double* b1 /* device or NULL */, void* ws, size_t ws_bytes, void* bws,
+                         size_t bws_bytes, void* stream, double* grad_x /* device, n*d */, int have_grad,
+                         double* out8 /* device, 8 */, double* out4 /* device, 4 */);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of evaluation requests from many HMC chains
  * (one request = one log-likelihood + gradient at new latent locations).

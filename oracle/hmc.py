@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import loglik_grad
+from . import bmds, loglik_grad
 
 NONE, BOX, DISC = 0, 1, 2
 MAX_BOUNCES = 64
@@ -88,6 +88,21 @@ def hawkes_grad_fn(t, params):
         st, _, gx, _ = loglik_grad(x, t, params, threads=True)
         return gx
     return g
+
+
+def bmds_grad_fn(delta, sigma):
+    """Location gradient of the Bayesian MDS log-likelihood (Sec. 2.2.3)."""
+    def g(x):
+        st, _, _, _, gx = bmds(x, delta, sigma)
+        return gx
+    return g
+
+
+def joint_grad_fn(t, params, delta, sigma):
+    """Gradient of the influenza model's log density over the locations
+    (Sec. 3): the Hawkes log-likelihood plus the MDS log-likelihood."""
+    gh, gb = hawkes_grad_fn(t, params), bmds_grad_fn(delta, sigma)
+    return lambda x: gh(x) + gb(x)
 
 
 def leapfrog(x, p, eps, steps, grad_fn, bound=NONE, b0=None, b1=None, g0=None):

@@ -55,8 +55,12 @@ def lib():
         L.hawkes_bmds_workspace_bytes.argtypes = [i64, ci]
         L.hawkes_bmds_workspace_bytes.restype = ctypes.c_size_t
         L.hawkes_bmds.argtypes = [dp, dp, i64, ci, ctypes.c_double, ci, vp, ctypes.c_size_t, vp, dp, dp]
+        L.hawkes_leapfrog_bmds.argtypes = [dp, dp, dp, i64, ci, pp, ci, dp, ctypes.c_double, ctypes.c_double, ci,
+                                           ci, dp, dp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp, dp, ci, dp,
+                                           dp]
         for f in (L.hawkes_loglik, L.hawkes_grad, L.hawkes_grad_async, L.hawkes_grad_timed, L.hawkes_event_terms,
-                  L.hawkes_mwg_step, L.hawkes_loglik_reweight, L.hawkes_leapfrog, L.hawkes_bmds):
+                  L.hawkes_mwg_step, L.hawkes_loglik_reweight, L.hawkes_leapfrog, L.hawkes_bmds,
+                  L.hawkes_leapfrog_bmds):
             f.restype = ci
         L.hawkes_strerror.argtypes = [ci]
         L.hawkes_strerror.restype = ctypes.c_char_p

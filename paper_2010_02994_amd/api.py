@@ -201,13 +201,7 @@ def loglik_reweight(t: torch.Tensor, d: int, params, terms: torch.Tensor,
 _BOUNDS = {None: _lib.BOUND_NONE, "none": _lib.BOUND_NONE, "box": _lib.BOUND_BOX, "disc": _lib.BOUND_DISC}
 
 
-def leapfrog(x: torch.Tensor, p: torch.Tensor, t: torch.Tensor, params, eps: float, steps: int, prec="mixed",
-             bound=None, b0: torch.Tensor | None = None, b1: torch.Tensor | None = None,
-             grad_x: torch.Tensor | None = None, have_grad: bool = False, out8: torch.Tensor | None = None):
-    """Enqueue `steps` leapfrog steps on the current stream; x and p (device
-    (N, D) float64, contiguous) move in place.  bound: None, "box" (b0/b1 =
-    lower/upper corners) or "disc" (b0 = centres, b1 = radii).  Returns
-    (grad_x at the final x, out8 = [loglik, 6 parameter gradients, status])."""
+def _trajectory_args(x, p, t, bound, b0, b1, grad_x, have_grad, out8):
     if not (x.is_contiguous() and p.is_contiguous() and x.dtype == torch.float64 and p.dtype == torch.float64):
         raise ValueError("x and p must be contiguous float64 device tensors")
     n, d = x.shape
@@ -221,12 +215,23 @@ def leapfrog(x: torch.Tensor, p: torch.Tensor, t: torch.Tensor, params, eps: flo
         want1 = (n, d) if kind == _lib.BOUND_BOX else (n,)
         if b0.shape != (n, d) or b1.shape != want1:
             raise ValueError("bound shape mismatch")
-    ws = workspace(n, d, prec, x.device)
     if grad_x is None:
         grad_x = torch.empty_like(x)
         have_grad = False
     if out8 is None:
         out8 = torch.empty(8, dtype=torch.float64, device=x.device)
+    return n, d, kind, b0, b1, grad_x, have_grad, out8
+
+
+def leapfrog(x: torch.Tensor, p: torch.Tensor, t: torch.Tensor, params, eps: float, steps: int, prec="mixed",
+             bound=None, b0: torch.Tensor | None = None, b1: torch.Tensor | None = None,
+             grad_x: torch.Tensor | None = None, have_grad: bool = False, out8: torch.Tensor | None = None):
+    """Enqueue `steps` leapfrog steps on the current stream; x and p (device
+    (N, D) float64, contiguous) move in place.  bound: None, "box" (b0/b1 =
+    lower/upper corners) or "disc" (b0 = centres, b1 = radii).  Returns
+    (grad_x at the final x, out8 = [loglik, 6 parameter gradients, status])."""
+    n, d, kind, b0, b1, grad_x, have_grad, out8 = _trajectory_args(x, p, t, bound, b0, b1, grad_x, have_grad, out8)
+    ws = workspace(n, d, prec, x.device)
     ps = params_struct(params)
     st = _lib.lib().hawkes_leapfrog(x.data_ptr(), p.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), _prec(prec),
                                     float(eps), int(steps), kind, b0.data_ptr() if b0 is not None else None,
@@ -238,7 +243,46 @@ def leapfrog(x: torch.Tensor, p: torch.Tensor, t: torch.Tensor, params, eps: flo
     return grad_x, out8
 
 
+def leapfrog_bmds(x: torch.Tensor, p: torch.Tensor, t: torch.Tensor, params, delta: torch.Tensor, sigma: float,
+                  eps: float, steps: int, prec="mixed", bound=None, b0: torch.Tensor | None = None,
+                  b1: torch.Tensor | None = None, grad_x: torch.Tensor | None = None, have_grad: bool = False,
+                  out8: torch.Tensor | None = None, out4: torch.Tensor | None = None):
+    """As `leapfrog`, for the influenza model's joint potential
+    -(Hawkes log-likelihood + MDS log-likelihood of delta): returns (grad_x,
+    out8 of the final Hawkes evaluation, out4 of the final MDS evaluation)."""
+    n, d, kind, b0, b1, grad_x, have_grad, out8 = _trajectory_args(x, p, t, bound, b0, b1, grad_x, have_grad, out8)
+    if delta.dtype != torch.float64 or delta.shape != (n, n) or not delta.is_contiguous():
+        raise ValueError("delta must be a contiguous (N, N) float64 device tensor")
+    if out4 is None:
+        out4 = torch.empty(4, dtype=torch.float64, device=x.device)
+    ws = workspace(n, d, prec, x.device)
+    bws = _bmds_workspace(n, d, x.device)
+    ps = params_struct(params)
+    st = _lib.lib().hawkes_leapfrog_bmds(x.data_ptr(), p.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps),
+                                         _prec(prec), delta.data_ptr(), float(sigma), float(eps), int(steps), kind,
+                                         b0.data_ptr() if b0 is not None else None,
+                                         b1.data_ptr() if b1 is not None else None, ws.data_ptr(), ws.numel(),
+                                         bws.data_ptr(), bws.numel(), _stream_ptr(x.device), grad_x.data_ptr(),
+                                         1 if have_grad else 0, out8.data_ptr(), out4.data_ptr())
+    if st != _lib.OK:
+        raise HawkesError(st, "hawkes_leapfrog_bmds")
+    return grad_x, out8, out4
+
+
 _bmds_ws: dict = {}
+
+
+def _bmds_workspace(n: int, d: int, device):
+    """MDS workspace for (n, d) on `device`, kept per (device, stream)."""
+    need = int(_lib.lib().hawkes_bmds_workspace_bytes(n, d))
+    if need == 0:
+        raise HawkesError(_lib.EINVAL, "bmds workspace size")
+    key = (device, _stream_ptr(device))
+    ws = _bmds_ws.get(key)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+        _bmds_ws[key] = ws
+    return ws
 
 
 def bmds(x: torch.Tensor, delta: torch.Tensor, sigma: float, prec="fp64", grad_x: torch.Tensor | None = None,
@@ -253,14 +297,7 @@ def bmds(x: torch.Tensor, delta: torch.Tensor, sigma: float, prec="fp64", grad_x
     n, d = x.shape
     if delta.shape != (n, n):
         raise ValueError("delta must be (N, N)")
-    need = int(_lib.lib().hawkes_bmds_workspace_bytes(n, d))
-    if need == 0:
-        raise HawkesError(_lib.EINVAL, "bmds workspace size")
-    key = (x.device, _stream_ptr(x.device))
-    ws = _bmds_ws.get(key)
-    if ws is None or ws.numel() < need:
-        ws = torch.empty(need, dtype=torch.uint8, device=x.device)
-        _bmds_ws[key] = ws
+    ws = _bmds_workspace(n, d, x.device)
     if want_grad and grad_x is None:
         grad_x = torch.empty_like(x)
     if out4 is None:

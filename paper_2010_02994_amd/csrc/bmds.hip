@@ -25,6 +25,7 @@
 
 #include "../../include/hawkes.h"
 #include "hawkes_common.hpp"
+#include "hawkes_internal.hpp"
 
 namespace hawkes {
 namespace bmds {
@@ -52,6 +53,7 @@ struct Args {
   double* ptile;  // ntiles x 4: sum of summands, sum of sigma terms, pairs, invalid deltas
   double* out4;   // [ell, d ell/d sigma, pairs, status]
   double* grad_x; // n x D or null
+  int accumulate; // 1: grad_x += the gradient (0: grad_x = the gradient)
 };
 
 // Wave totals in lane 63: inclusive row scans by DPP row_shr 1, 2, 4, 8, then
@@ -285,7 +287,10 @@ __global__ void __launch_bounds__(256) k_bmds_reduce(Args a) {
 #pragma unroll
     for (int q = 0; q < D; ++q) g[q] += a.pcol[((band_offset(Ib) + J) * kTC + c) * D + q];
 #pragma unroll
-  for (int q = 0; q < D; ++q) a.grad_x[(int64_t)n * D + q] = g[q];
+  for (int q = 0; q < D; ++q) {
+    const int64_t e = (int64_t)n * D + q;
+    a.grad_x[e] = a.accumulate ? a.grad_x[e] + g[q] : g[q];
+  }
 }
 
 struct Pieces {
@@ -314,20 +319,10 @@ static void launch(const Args& a, int prec, hipStream_t s) {
 }
 
 }  // namespace bmds
-}  // namespace hawkes
 
-extern "C" {
-
-size_t hawkes_bmds_workspace_bytes(int64_t n, int d) {
-  if (n < 2 || n > (int64_t(1) << 20) || d < 1 || d > hawkes::kMaxD) return 0;
-  int64_t ntiles;
-  int nb;
-  return hawkes::bmds::pieces(n, d, ntiles, nb).total;
-}
-
-int hawkes_bmds(const double* x, const double* delta, int64_t n, int d, double sigma, int prec, void* ws,
-                size_t ws_bytes, void* stream, double* out4, double* grad_x) {
-  using namespace hawkes::bmds;
+int bmds_enqueue(const double* x, const double* delta, int64_t n, int d, double sigma, int prec, void* ws,
+                 size_t ws_bytes, hipStream_t s, double* out4, double* grad_x, bool accumulate) {
+  using namespace bmds;
   if (!x || !delta || !ws || !out4) return HAWKES_EINVAL;
   if (prec != HAWKES_FP64 && prec != HAWKES_MIXED) return HAWKES_EINVAL;
   const size_t need = hawkes_bmds_workspace_bytes(n, d);
@@ -347,7 +342,7 @@ int hawkes_bmds(const double* x, const double* delta, int64_t n, int d, double s
   a.ptile = reinterpret_cast<double*>(w + pc.ptile);
   a.out4 = out4;
   a.grad_x = grad_x;
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  a.accumulate = accumulate ? 1 : 0;
   (void)hipGetLastError();
   switch (d) {
     case 1: launch<1>(a, prec, s); break;
@@ -360,6 +355,23 @@ int hawkes_bmds(const double* x, const double* delta, int64_t n, int d, double s
     case 8: launch<8>(a, prec, s); break;
   }
   return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+}
+
+}  // namespace hawkes
+
+extern "C" {
+
+size_t hawkes_bmds_workspace_bytes(int64_t n, int d) {
+  if (n < 2 || n > (int64_t(1) << 20) || d < 1 || d > hawkes::kMaxD) return 0;
+  int64_t ntiles;
+  int nb;
+  return hawkes::bmds::pieces(n, d, ntiles, nb).total;
+}
+
+int hawkes_bmds(const double* x, const double* delta, int64_t n, int d, double sigma, int prec, void* ws,
+                size_t ws_bytes, void* stream, double* out4, double* grad_x) {
+  return hawkes::bmds_enqueue(x, delta, n, d, sigma, prec, ws, ws_bytes, static_cast<hipStream_t>(stream), out4,
+                              grad_x, false);
 }
 
 }  // extern "C"

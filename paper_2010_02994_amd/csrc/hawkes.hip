@@ -227,7 +227,7 @@ static thread_local StageTimer* g_timer = nullptr;
 
 static inline void mark(hipStream_t s, int stage) {
   if (g_timer) {
-    hipEventRecord(g_timer->ev[stage], s);
+    (void)hipEventRecord(g_timer->ev[stage], s);
     g_timer->used = stage + 1;
   }
 }
@@ -512,8 +512,8 @@ int hawkes_grad_timed(const double* x, const double* t, int64_t n, int d, const 
   hawkes::g_timer = nullptr;
   for (int k = 0; k < hawkes::kNumStages; ++k) stage_ms[k] = 0.f;
   if (st == HAWKES_OK || st == HAWKES_EZERORATE) {
-    hipEventSynchronize(tm.ev[tm.used - 1]);
-    for (int k = 0; k + 1 < tm.used; ++k) hipEventElapsedTime(&stage_ms[k], tm.ev[k], tm.ev[k + 1]);
+    (void)hipEventSynchronize(tm.ev[tm.used - 1]);
+    for (int k = 0; k + 1 < tm.used; ++k) (void)hipEventElapsedTime(&stage_ms[k], tm.ev[k], tm.ev[k + 1]);
   }
   return st;
 }

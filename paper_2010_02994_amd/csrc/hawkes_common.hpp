@@ -25,6 +25,14 @@ namespace hawkes {
 #ifndef HK_GRAD_EXP_STEPS
 #define HK_GRAD_EXP_STEPS 1
 #endif
+// Column steps of a tile's 64-step sweep unrolled per loop trip in the mixed
+// rate and gradient passes (16 and 32 measured fastest on gfx950).
+#ifndef HK_RATE_UNROLL
+#define HK_RATE_UNROLL 16
+#endif
+#ifndef HK_GRAD_UNROLL
+#define HK_GRAD_UNROLL 32
+#endif
 constexpr int kWaves = HK_WAVES;        // waves per workgroup
 constexpr int kThreads = 64 * kWaves;   // workgroup size
 constexpr int kRowsPerLane = HK_ROWS_PER_LANE;  // rows each lane owns in the pair passes

@@ -38,5 +38,9 @@ int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const Batc
 // grad_x is not null, the gradient pass) with no host synchronization.
 int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
               size_t ws_bytes, void* stream, double* out8, double* grad_x, double* terms = nullptr);
+// Enqueue one Bayesian MDS evaluation; accumulate: grad_x += its location
+// gradient instead of grad_x = it.
+int bmds_enqueue(const double* x, const double* delta, int64_t n, int d, double sigma, int prec, void* ws,
+                 size_t ws_bytes, hipStream_t s, double* out4, double* grad_x, bool accumulate);
 
 }  // namespace hawkes

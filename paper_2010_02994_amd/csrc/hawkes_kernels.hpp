@@ -571,7 +571,8 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
   // their exps issued back to back, so no exp result is consumed by the very
   // next instruction; the steps are then accumulated in order.
   constexpr int KS = kRateExpSteps;
-#pragma unroll (8 / KS)
+  constexpr int UN = HK_RATE_UNROLL / KS;
+#pragma unroll UN
   for (int k0 = 0; k0 < 64; k0 += KS) {
     float r2v[KS][R], dtv[KS][R], ebv[KS][R], esv[KS][R];
 #pragma unroll
@@ -753,7 +754,8 @@ __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const ty
   // exponents of kGradExpSteps steps first, exps back to back, then the
   // steps in order (as in the rate pass)
   constexpr int KS = kGradExpSteps;
-#pragma unroll (8 / KS)
+  constexpr int UN = HK_GRAD_UNROLL / KS;
+#pragma unroll UN
   for (int k0 = 0; k0 < 64; k0 += KS) {
     float dx[KS][R][D], r2[KS][R], dt[KS][R], eb[KS][R], es[KS][R], pbj[KS];
 #pragma unroll

@@ -8,7 +8,9 @@
 //   reflections (momentum mirrored at each wall);  g = grad ell(x);
 //   p += eps g (eps/2 on the last step) }
 // where every gradient is the full evaluation of the library, enqueued on the
-// caller's stream; nothing returns to the host between steps.
+// caller's stream; nothing returns to the host between steps.  For the
+// influenza model ell is the Hawkes log-likelihood plus the Bayesian MDS
+// log-likelihood of the same locations (Sec. 3), and g sums both gradients.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -158,6 +160,58 @@ static void kick_fly_d(int d, double* x, double* p, const double* g, int n, doub
   }
 }
 
+// The optional second term of the potential: the Bayesian MDS likelihood of
+// the same locations (the influenza model, whose HMC over the latent
+// locations needs the gradients of both the Hawkes and the MDS likelihoods).
+struct MdsTerm {
+  const double* delta;
+  double sigma;
+  void* ws;
+  size_t ws_bytes;
+  double* out4;
+};
+
+// grad_x = the location gradient of the potential's log density at x.
+static int gradient(double* x, const double* t, int64_t n, int d, const hawkes_params_t* prm, int prec, void* ws,
+                    size_t ws_bytes, hipStream_t s, double* grad_x, double* out8, const MdsTerm* mds) {
+  int st = run_async(x, t, n, d, prm, prec, ws, ws_bytes, s, out8, grad_x);
+  if (st == HAWKES_OK && mds)
+    st = bmds_enqueue(x, mds->delta, n, d, mds->sigma, prec & ~HAWKES_CULL, mds->ws, mds->ws_bytes, s, mds->out4,
+                      grad_x, true);
+  return st;
+}
+
+static int leapfrog(double* x, double* p, const double* t, int64_t n, int d, const hawkes_params_t* prm, int prec,
+                    double eps, int steps, int bound, const double* b0, const double* b1, void* ws, size_t ws_bytes,
+                    void* stream, double* grad_x, int have_grad, double* out8, const MdsTerm* mds) {
+  if (!x || !p || !t || !prm || !ws || !grad_x || !out8) return HAWKES_EINVAL;
+  if (steps < 1 || !std::isfinite(eps) || !(eps > 0.0)) return HAWKES_EINVAL;
+  if (bound != HAWKES_BOUND_NONE && bound != HAWKES_BOUND_BOX && bound != HAWKES_BOUND_DISC) return HAWKES_EINVAL;
+  if (bound != HAWKES_BOUND_NONE && (!b0 || !b1)) return HAWKES_EINVAL;
+  const size_t need = hawkes_workspace_bytes(n, d, prec);
+  if (need == 0 || ws_bytes < need) return HAWKES_EINVAL;
+  if (!valid_params(prm)) return HAWKES_EPARAM;
+  if (mds) {
+    if (!mds->delta || !mds->ws || !mds->out4) return HAWKES_EINVAL;
+    const size_t bneed = hawkes_bmds_workspace_bytes(n, d);
+    if (bneed == 0 || mds->ws_bytes < bneed) return HAWKES_EINVAL;
+    if (!std::isfinite(mds->sigma) || !(mds->sigma > 0.0)) return HAWKES_EPARAM;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int st = HAWKES_OK;
+  if (!have_grad) st = gradient(x, t, n, d, prm, prec, ws, ws_bytes, s, grad_x, out8, mds);
+  for (int k = 0; k < steps && st == HAWKES_OK; ++k) {
+    (void)hipGetLastError();
+    kick_fly_d(d, x, p, grad_x, (int)n, k == 0 ? 0.5 * eps : eps, eps, bound, b0, b1, true, s);
+    if (hipGetLastError() != hipSuccess) return HAWKES_EDEVICE;
+    st = gradient(x, t, n, d, prm, prec, ws, ws_bytes, s, grad_x, out8, mds);
+  }
+  if (st != HAWKES_OK) return st;
+  (void)hipGetLastError();
+  kick_fly_d(d, x, p, grad_x, (int)n, 0.5 * eps, eps, bound, b0, b1, false, s);
+  return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+}
+
 }  // namespace hmc
 }  // namespace hawkes
 
@@ -166,27 +220,17 @@ extern "C" {
 int hawkes_leapfrog(double* x, double* p, const double* t, int64_t n, int d, const hawkes_params_t* prm, int prec,
                     double eps, int steps, int bound, const double* b0, const double* b1, void* ws, size_t ws_bytes,
                     void* stream, double* grad_x, int have_grad, double* out8) {
-  using namespace hawkes::hmc;
-  if (!x || !p || !t || !prm || !ws || !grad_x || !out8) return HAWKES_EINVAL;
-  if (steps < 1 || !std::isfinite(eps) || !(eps > 0.0)) return HAWKES_EINVAL;
-  if (bound != HAWKES_BOUND_NONE && bound != HAWKES_BOUND_BOX && bound != HAWKES_BOUND_DISC) return HAWKES_EINVAL;
-  if (bound != HAWKES_BOUND_NONE && (!b0 || !b1)) return HAWKES_EINVAL;
-  const size_t need = hawkes_workspace_bytes(n, d, prec);
-  if (need == 0 || ws_bytes < need) return HAWKES_EINVAL;
-  if (!hawkes::valid_params(prm)) return HAWKES_EPARAM;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  int st = HAWKES_OK;
-  if (!have_grad) st = hawkes::run_async(x, t, n, d, prm, prec, ws, ws_bytes, stream, out8, grad_x);
-  for (int k = 0; k < steps && st == HAWKES_OK; ++k) {
-    (void)hipGetLastError();
-    kick_fly_d(d, x, p, grad_x, (int)n, k == 0 ? 0.5 * eps : eps, eps, bound, b0, b1, true, s);
-    if (hipGetLastError() != hipSuccess) return HAWKES_EDEVICE;
-    st = hawkes::run_async(x, t, n, d, prm, prec, ws, ws_bytes, stream, out8, grad_x);
-  }
-  if (st != HAWKES_OK) return st;
-  (void)hipGetLastError();
-  kick_fly_d(d, x, p, grad_x, (int)n, 0.5 * eps, eps, bound, b0, b1, false, s);
-  return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+  return hawkes::hmc::leapfrog(x, p, t, n, d, prm, prec, eps, steps, bound, b0, b1, ws, ws_bytes, stream, grad_x,
+                               have_grad, out8, nullptr);
+}
+
+int hawkes_leapfrog_bmds(double* x, double* p, const double* t, int64_t n, int d, const hawkes_params_t* prm,
+                         int prec, const double* delta, double sigma, double eps, int steps, int bound,
+                         const double* b0, const double* b1, void* ws, size_t ws_bytes, void* bws, size_t bws_bytes,
+                         void* stream, double* grad_x, int have_grad, double* out8, double* out4) {
+  const hawkes::hmc::MdsTerm mds{delta, sigma, bws, bws_bytes, out4};
+  return hawkes::hmc::leapfrog(x, p, t, n, d, prm, prec, eps, steps, bound, b0, b1, ws, ws_bytes, stream, grad_x,
+                               have_grad, out8, &mds);
 }
 
 }  // extern "C"

@@ -246,3 +246,21 @@ def bmds_case(seed: int, n: int, d: int, missing: float = 0.0, sigma: float = 0.
     x = z + 0.1 * rng.standard_normal((n, d))
     return BmdsCase(f"bmds_s{seed}_n{n}_d{d}", np.ascontiguousarray(x), np.ascontiguousarray(delta), float(sigma),
                     seed)
+
+
+def flu_case(seed: int = 1004, n: int = 4733, d: int = 6, groups: int = 64, years: float = 12.0):
+    """Joint Hawkes + Bayesian MDS workload in the shape of the influenza
+    application (Sec. 4.3): `n` cases in `groups` countries over `years`
+    years, latent locations in d dimensions with the country-by-country
+    dissimilarities of `bmds_case`, case times uniform over the span (sorted,
+    no ties).  Returns (Workload with the Hawkes inputs, BmdsCase)."""
+    c = bmds_case(seed, n, d, groups=groups)
+    rng = np.random.default_rng(seed + 1)
+    t = np.sort(rng.uniform(0.0, 365.0 * years, size=n))
+    assert np.all(np.diff(t) > 0)
+    # (mu0, tau_x, tau_t, theta, omega, h): background kernel wide in the
+    # latent space and half a year in time, self-excitation within a country
+    params = np.array([0.5, 1.0, 180.0, 0.5, 0.01, 0.2])
+    wl = Workload(f"flu_n{n}_d{d}_{groups}countries", c.x.copy(), t, params, seed=seed)
+    return wl, c
+

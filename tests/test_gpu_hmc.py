@@ -3,6 +3,7 @@ disc walls) against the oracle's trajectories."""
 import numpy as np
 import pytest
 
+import oracle
 from oracle import hmc
 from paper_2010_02994_amd import workloads as W
 from tests.gpu_util import say
@@ -147,3 +148,51 @@ def test_leapfrog_graph_replay_matches_eager():
             _ = (xs * 2).sum().item()   # unrelated eager work between replays
             for a, b in zip(got, eager[k]):
                 assert np.array_equal(a, b), (prec, k)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_leapfrog_bmds_matches_oracle(prec):
+    """The influenza model's joint trajectory (Hawkes + MDS potential, D = 6)
+    against the oracle's leapfrog with the summed gradients."""
+    import torch
+    from paper_2010_02994_amd import api
+    w, c = W.flu_case(seed=107, n=700, d=6, groups=16, years=4.0)
+    rng = np.random.default_rng(107)
+    p0 = rng.standard_normal(w.x.shape)
+    eps, steps = 0.002, 10
+    say(f"case leapfrog+bmds {prec} n={w.n} d=6")
+    x, p, t, dl = _dev(w.x), _dev(p0), _dev(w.t), _dev(c.delta)
+    g, out8, out4 = api.leapfrog_bmds(x, p, t, w.params, dl, c.sigma, eps, steps, prec=prec)
+    torch.cuda.synchronize()
+    x, p, g, out8, out4 = (v.cpu().numpy() for v in (x, p, g, out8, out4))
+    xr, pr, gr = hmc.leapfrog(w.x, p0, eps, steps, hmc.joint_grad_fn(w.t, w.params, c.delta, c.sigma))
+    e_x = np.linalg.norm(x - xr) / np.linalg.norm(xr - w.x)
+    e_dp = np.linalg.norm(p - pr) / np.linalg.norm(pr - p0)
+    e_g = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    say(f"  err displacement {e_x:.2e} momentum change {e_dp:.2e} grad {e_g:.2e}")
+    assert out8[7] == 0 and out4[3] == 0
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    assert e_x <= tol and e_dp <= tol and e_g <= tol
+    st, ll_b, _, M, _ = oracle.bmds(xr, c.delta, c.sigma)
+    assert out4[2] == M
+    assert abs(out4[0] - ll_b) <= (1e-10 if prec == "fp64" else 1e-5) * abs(ll_b)
+
+
+def test_leapfrog_bmds_gradient_is_the_sum_of_the_single_calls():
+    """At the trajectory's end, the returned gradient equals the Hawkes and
+    MDS location gradients of the single entry points added (bitwise), and
+    out8/out4 equal those calls' outputs."""
+    import torch
+    from paper_2010_02994_amd import api
+    w, c = W.flu_case(seed=108, n=500, d=6, groups=12, years=3.0)
+    rng = np.random.default_rng(108)
+    say("case leapfrog+bmds gradient sum")
+    for prec in ("mixed", "fp64"):
+        x, p, t, dl = _dev(w.x), _dev(rng.standard_normal(w.x.shape)), _dev(w.t), _dev(c.delta)
+        g, out8, out4 = api.leapfrog_bmds(x, p, t, w.params, dl, c.sigma, 0.002, 3, prec=prec)
+        gh = torch.empty_like(x)
+        o8 = api.grad_async(x, t, w.params, prec=prec, grad_x=gh)
+        o4, gb = api.bmds(x, dl, c.sigma, prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(g, gh + gb), prec
+        assert torch.equal(out8, o8) and torch.equal(out4, o4), prec

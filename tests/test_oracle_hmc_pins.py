@@ -119,3 +119,29 @@ def test_hawkes_leapfrog_energy_error_is_second_order():
         x, p, _ = hmc.leapfrog(w.x, p0, eps, steps, g)
         errs.append(abs(H(x, p) - h0))
     assert 2.5 < errs[0] / errs[1] < 6.0 and 2.5 < errs[1] / errs[2] < 6.0
+
+
+def test_joint_leapfrog_energy_error_is_second_order_and_reversible():
+    """The influenza model's potential -(ell_hawkes + ell_mds): the joint
+    Hamiltonian drifts by O(eps^2), and the trajectory runs back to its start.
+    A wrong sign or a missing term in either gradient breaks the energy order."""
+    w, c = W.flu_case(seed=9, n=30, d=3, groups=5, years=1.0)
+    rng = np.random.default_rng(9)
+    p0 = rng.standard_normal(w.x.shape)
+    g = hmc.joint_grad_fn(w.t, w.params, c.delta, c.sigma)
+
+    def H(x, p):
+        ll_h = oracle.loglik_grad(x, w.t, w.params)[1]
+        ll_b = oracle.bmds(x, c.delta, c.sigma)[1]
+        return -(ll_h + ll_b) + 0.5 * float(np.sum(p * p))
+
+    h0 = H(w.x, p0)
+    errs = []
+    for eps, steps in ((0.004, 10), (0.002, 20), (0.001, 40)):
+        x, p, _ = hmc.leapfrog(w.x, p0, eps, steps, g)
+        errs.append(abs(H(x, p) - h0))
+    assert 2.5 < errs[0] / errs[1] < 6.0 and 2.5 < errs[1] / errs[2] < 6.0
+    x1, p1, _ = hmc.leapfrog(w.x, p0, 0.004, 10, g)
+    x2, p2, _ = hmc.leapfrog(x1, -p1, 0.004, 10, g)
+    np.testing.assert_allclose(x2, w.x, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(-p2, p0, rtol=0, atol=1e-8)
