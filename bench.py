@@ -351,27 +351,26 @@ def flu_leapfrog_bench(dev, trajectories: int):
     log-likelihood gradient plus the Bayesian MDS gradient."""
     import torch
     from paper_2010_02994_amd import api, workloads
-    w, c = workloads.flu_case()
+    w, dl, sigma = workloads.flu_case_device(device=dev)
     t = torch.tensor(w.t, device=dev)
-    dl = torch.tensor(c.delta, device=dev)
     rng = np.random.default_rng(12)
     steps, eps = 20, 0.001
     out = {"workload": f"{w.name}: 20-step leapfrog on the Hawkes + MDS potential", "steps": steps, "eps": eps}
     for prec in ("mixed", "fp64"):
         x = torch.tensor(w.x, device=dev)
         p = torch.tensor(rng.standard_normal(w.x.shape), device=dev)
-        g, out8, out4 = api.leapfrog_bmds(x, p, t, w.params, dl, c.sigma, eps, steps, prec=prec)
+        g, out8, out4 = api.leapfrog_bmds(x, p, t, w.params, dl, sigma, eps, steps, prec=prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(trajectories):
             p.copy_(torch.tensor(rng.standard_normal(w.x.shape), device=dev))
-            g, out8, out4 = api.leapfrog_bmds(x, p, t, w.params, dl, c.sigma, eps, steps, prec=prec, grad_x=g,
+            g, out8, out4 = api.leapfrog_bmds(x, p, t, w.params, dl, sigma, eps, steps, prec=prec, grad_x=g,
                                               have_grad=True, out8=out8, out4=out4)
         torch.cuda.synchronize()
         el = (time.perf_counter() - t0) / trajectories
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
-            api.leapfrog_bmds(x, p, t, w.params, dl, c.sigma, eps, steps, prec=prec, grad_x=g, have_grad=True,
+            api.leapfrog_bmds(x, p, t, w.params, dl, sigma, eps, steps, prec=prec, grad_x=g, have_grad=True,
                               out8=out8, out4=out4)
         graph.replay()
         torch.cuda.synchronize()
@@ -391,25 +390,13 @@ def bmds_bench(dev, reps: int):
     """Bayesian MDS log-likelihood + gradients: the influenza-like case
     (N = 4,733 cases in D = 6, 64 countries, dissimilarities between country
     centres, same-country pairs unobserved) and a larger N = 20,000, D = 6 case
-    whose dissimilarities are generated on the device (|z_n - z_n'| plus folded
-    normal noise).  The pass reads the strict lower triangle of the float64
+    (|z_n - z_n'| plus folded normal noise), both drawn on the device.  The pass reads the strict lower triangle of the float64
     matrix once, so its roofline is HBM: 4 N (N - 1) bytes per evaluation."""
     import torch
     from paper_2010_02994_amd import api, workloads
     out = {}
-    c = workloads.bmds_case(4733, 4733, 6, groups=64)
-    cases = [("flu_n4733_d6_64countries", torch.tensor(c.x, device=dev), torch.tensor(c.delta, device=dev), c.sigma)]
-    del c
-    g = torch.Generator(device=dev)
-    g.manual_seed(20000)
-    n = 20000
-    z = torch.randn((n, 6), generator=g, device=dev, dtype=torch.float64)
-    dl = torch.cdist(z, z)
-    noise = torch.randn((n, n), generator=g, device=dev, dtype=torch.float64).tril_(-1)
-    dl.add_(0.3 * (noise + noise.T)).abs_()
-    del noise
-    x = z + 0.1 * torch.randn((n, 6), generator=g, device=dev, dtype=torch.float64)
-    cases.append(("dense_n20000_d6", x, dl, 0.3))
+    cases = [("flu_n4733_d6_64countries",) + workloads.bmds_case_device(4733, 4733, 6, groups=64, device=dev),
+             ("dense_n20000_d6",) + workloads.bmds_case_device(20000, 20000, 6, device=dev)]
     for name, x, dl, sigma in cases:
         n = x.shape[0]
         rec = {"n": n, "d": int(x.shape[1]), "delta_bytes_read": 4 * n * (n - 1)}

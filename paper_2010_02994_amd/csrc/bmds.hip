@@ -11,12 +11,14 @@
 // the pair arithmetic is float32 and close to balanced in float64.
 //
 // Tiles: row band I (rows [64 I, 64 I + 64)) meets column chunks
-// J = 0 .. floor(I / 4) of 256 columns.  A workgroup of 256 lanes takes one
-// tile, one column per lane, and walks the 64 rows: the lanes of a row read
-// consecutive delta entries (one coalesced 2 KB row segment per step).  Column
-// sums stay in each lane; the row sums are wave totals formed with DPP row
-// shifts and row broadcasts (no LDS traffic), then added over the four waves
-// in a fixed order.  Per-tile partials are reduced per event in a fixed order.
+// J = 0 .. floor(I / 4) of 256 columns.  A workgroup takes one tile, C columns
+// per lane (C runs of 64 columns per wave), and walks the 64 rows: the lanes
+// of a wave read consecutive delta entries (coalesced 512 B row segments).
+// Column sums stay in each lane.  A row's sum is first formed in the lane over
+// its C columns, then over each 16-lane row of the wave by DPP row shifts; the
+// partials of the 16-lane rows and of the waves are added at the end in a
+// fixed order.  With C columns per lane the cross-lane work per pair falls by
+// C.  Per-tile partials are reduced per event in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -31,10 +33,18 @@ namespace hawkes {
 namespace bmds {
 
 constexpr int kTR = 64;        // rows per tile
-constexpr int kTC = 256;       // columns per tile (one per lane of the workgroup)
-constexpr int kThreads = 256;
+constexpr int kTC = 256;       // columns per tile
 constexpr int kFinalThreads = 1024;
 constexpr int kPrefetch = 8;   // rows whose entries are loaded ahead of their arithmetic
+#ifndef HK_BMDS_COLS_MIXED
+#define HK_BMDS_COLS_MIXED 4
+#endif
+#ifndef HK_BMDS_COLS_FP64
+#define HK_BMDS_COLS_FP64 2
+#endif
+constexpr int kColsMixed = HK_BMDS_COLS_MIXED;   // columns per lane, float32 pairs, many tiles
+constexpr int kColsFp64 = HK_BMDS_COLS_FP64;     // columns per lane, float64 pairs, many tiles
+constexpr int64_t kWideTiles = 4096;             // fewer tiles: one column per lane
 
 // First tile of row band I: sum over I' < I of (floor(I'/4) + 1).
 __host__ __device__ inline int64_t band_offset(int64_t I) {
@@ -56,10 +66,8 @@ struct Args {
   int accumulate; // 1: grad_x += the gradient (0: grad_x = the gradient)
 };
 
-// Wave totals in lane 63: inclusive row scans by DPP row_shr 1, 2, 4, 8, then
-// row_bcast:15 (lane 63 gains lane 47, row 2's total) and row_bcast:31 (lane
-// 63 gains lane 31, by then rows 0 and 1's total); lanes without a source
-// read 0.
+// DPP reads of a lane in the same row of 16 (row shifts); lanes without a
+// source read 0.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ float dpp_f(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, true));
@@ -75,25 +83,6 @@ template <int CTRL, int ROWS, typename R>
 __device__ __forceinline__ R dpp_step(R v) {
   if constexpr (std::is_same<R, float>::value) return dpp_f<CTRL, ROWS>(v);
   else return dpp_d<CTRL, ROWS>(v);
-}
-// K independent totals, step by step across the K values so that no DPP read
-// waits on the add just before it.
-template <int K, typename R>
-__device__ __forceinline__ void wave_totals_lane63(R* v) {
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x111, 0xf>(v[k]);  // row_shr:1
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x112, 0xf>(v[k]);  // row_shr:2
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x114, 0xf>(v[k]);  // row_shr:4
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x118, 0xf>(v[k]);  // row_shr:8
-  // all rows enabled: rows 0 and 1 may pick up other values, but lane 63
-  // only ever reads lane 47 (row 2's scan) and lane 31 (rows 0 and 1's total)
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x142, 0xf>(v[k]);  // row_bcast:15
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] += dpp_step<0x143, 0xf>(v[k]);  // row_bcast:31
 }
 
 // erfc(w) for w >= 0 in float32: the Chebyshev-fitted form
@@ -118,10 +107,13 @@ __device__ __forceinline__ float erfc_cheb(float w) {
 // Summand, sigma term and gradient coefficient of one observed pair.  The
 // upper tail q = 1 - Phi(z) is formed directly, so log Phi keeps small tails.
 template <typename R>
-__device__ __forceinline__ void pair_terms(R dist, R delta, R inv_sigma, R inv_s2, R& term, R& dsig, R& coef) {
-  const R z = dist * inv_sigma;
-  const R res = delta - dist;
+__device__ __forceinline__ void pair_terms(R r2, R delta, R inv_sigma, R inv_s2, R& term, R& dsig, R& coef) {
   if constexpr (std::is_same<R, float>::value) {
+    // d and 1/d from one reciprocal square root (d = 0 adds no direction)
+    const float rs = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+    const float dist = r2 * rs;
+    const float z = dist * inv_sigma;
+    const float res = delta - dist;
     const float q = 0.5f * erfc_cheb(z * 0.70710678118654752f);
     const float phi = 1.0f - q;
     const float lphi = __builtin_amdgcn_logf(phi) * 0.69314718055994531f;
@@ -129,8 +121,11 @@ __device__ __forceinline__ void pair_terms(R dist, R delta, R inv_sigma, R inv_s
     const float rho = pdf * __builtin_amdgcn_rcpf(phi);
     term = -0.5f * res * res * inv_s2 - lphi;
     dsig = (res * res * inv_s2 + rho * z) * inv_sigma;
-    coef = dist > 0.0f ? (res * inv_s2 - rho * inv_sigma) * __builtin_amdgcn_rcpf(dist) : 0.0f;
+    coef = (res * inv_s2 - rho * inv_sigma) * rs;
   } else {
+    const double dist = sqrt(r2);
+    const double z = dist * inv_sigma;
+    const double res = delta - dist;
     const double q = 0.5 * erfc(z * 0.70710678118654752440);
     const double lphi = log1p(-q);
     const double pdf = 0.39894228040143267794 * exp(-0.5 * z * z);
@@ -141,12 +136,29 @@ __device__ __forceinline__ void pair_terms(R dist, R delta, R inv_sigma, R inv_s
   }
 }
 
-template <int D, bool MIX>
-__global__ void __launch_bounds__(kThreads) k_bmds_tiles(Args a) {
+// Lanes per workgroup and prefetched rows of a tile pass with C columns per lane.
+#ifndef HK_BMDS_PRE_WIDE
+#define HK_BMDS_PRE_WIDE 4
+#endif
+template <int C>
+struct TileShape {
+  static constexpr int kLanes = kTC / C;                         // workgroup size
+  static constexpr int kWavesT = kLanes / 64;
+  static constexpr int kPre = C >= 4 ? HK_BMDS_PRE_WIDE : kPrefetch;   // rows loaded ahead
+  // partial row sums per wave: one column per lane reduces over the whole
+  // wave (row broadcasts 15 and 31 after the row shifts); wider lanes stop at
+  // the four 16-lane rows
+  static constexpr int kParts = C == 1 ? 1 : 4;
+};
+
+template <int D, bool MIX, int C>
+__global__ void __launch_bounds__(TileShape<C>::kLanes) k_bmds_tiles(Args a) {
   using R = typename std::conditional<MIX, float, double>::type;
+  using TS = TileShape<C>;
+  constexpr int NL = TS::kLanes, NW = TS::kWavesT, PRE = TS::kPre, NP = TS::kParts;
   __shared__ R s_x[kTR][D];
-  __shared__ R s_row[kThreads / 64][kTR][D];
-  __shared__ double sh[4 * kThreads];
+  __shared__ R s_row[NW][kTR][NP][D];   // partial row sums
+  __shared__ double sh[4 * NL];
   const int64_t tile = blockIdx.x;
   int lo = 0, hi = a.nb - 1;   // band: largest I with band_offset(I) <= tile
   while (lo < hi) {
@@ -157,86 +169,127 @@ __global__ void __launch_bounds__(kThreads) k_bmds_tiles(Args a) {
   const int I = lo;
   const int J = (int)(tile - band_offset(I));
   const int i0 = I * kTR;
-  const int j = J * kTC + threadIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int e = threadIdx.x; e < kTR * D; e += kThreads) {
+  // columns of this lane: C runs of 64, so each row's loads stay coalesced
+  int jc[C], jl[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    jl[c] = w * 64 * C + c * 64 + lane;
+    jc[c] = J * kTC + jl[c];
+  }
+  for (int e = threadIdx.x; e < kTR * D; e += NL) {
     const int r = e / D, q = e % D;
     const int i = i0 + r;
     s_x[r][q] = i < a.n ? (R)a.x[(int64_t)i * D + q] : R(0);
   }
-  R xj[D], g[D];
+  R xj[C][D], g[C][D], tsum[C], dsum[C];
+  int cnt = 0, bad = 0;
 #pragma unroll
-  for (int q = 0; q < D; ++q) {
-    xj[q] = j < a.n ? (R)a.x[(int64_t)j * D + q] : R(0);
-    g[q] = R(0);
+  for (int c = 0; c < C; ++c) {
+    tsum[c] = R(0);
+    dsum[c] = R(0);
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      xj[c][q] = jc[c] < a.n ? (R)a.x[(int64_t)jc[c] * D + q] : R(0);
+      g[c][q] = R(0);
+    }
   }
   const R inv_sigma = (R)a.inv_sigma, inv_s2 = (R)a.inv_s2;
-  R tsum = R(0), dsum = R(0);
-  int cnt = 0, bad = 0;
   __syncthreads();
   const int rows = min(kTR, a.n - i0);
-  for (int r0 = 0; r0 < rows; r0 += kPrefetch) {
-    // the next rows' entries first, so kPrefetch loads are in flight at once;
+  for (int r0 = 0; r0 < rows; r0 += PRE) {
+    // the next rows' entries first, so PRE x C loads are in flight at once;
     // every load is issued (its address clamped into the matrix) and the
     // entries outside the triangle are masked afterwards, so no branch
-    // separates the loads and each row waits only for its own entry
-    double v[kPrefetch];
-    const int jc = min(j, a.n - 1);
+    // separates the loads and each row waits only for its own entries
+    double v[PRE][C];
 #pragma unroll
-    for (int u = 0; u < kPrefetch; ++u) {
+    for (int u = 0; u < PRE; ++u) {
       const int i = min(i0 + r0 + u, a.n - 1);
-      v[u] = a.delta[(int64_t)i * a.n + jc];
-    }
-
 #pragma unroll
-    for (int u = 0; u < kPrefetch; ++u) {
+      for (int c = 0; c < C; ++c) v[u][c] = a.delta[(int64_t)i * a.n + min(jc[c], a.n - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
       const int r = r0 + u;
       if (r >= rows) break;
       R gi[D];
 #pragma unroll
       for (int q = 0; q < D; ++q) gi[q] = R(0);
-      if (j < i0 + r && !isnan(v[u])) {
-        if (v[u] < 0.0 || isinf(v[u])) {
-          bad += 1;
-        } else {
-          R diff[D], r2 = R(0);
 #pragma unroll
-          for (int q = 0; q < D; ++q) {
-            diff[q] = s_x[r][q] - xj[q];
-            r2 += diff[q] * diff[q];
-          }
-          R term, dsig, coef;
-          R dist;
-          if constexpr (MIX) dist = __builtin_amdgcn_sqrtf(r2);
-          else dist = sqrt(r2);
-          pair_terms<R>(dist, (R)v[u], inv_sigma, inv_s2, term, dsig, coef);
-          tsum += term;
-          dsum += dsig;
-          cnt += 1;
+      for (int c = 0; c < C; ++c) {
+        const double dv = v[u][c];
+        if (jc[c] < i0 + r && !isnan(dv)) {
+          if (dv < 0.0 || isinf(dv)) {
+            bad += 1;
+          } else {
+            R diff[D], r2 = R(0);
 #pragma unroll
-          for (int q = 0; q < D; ++q) {
-            gi[q] = coef * diff[q];
-            g[q] -= gi[q];
+            for (int q = 0; q < D; ++q) {
+              diff[q] = s_x[r][q] - xj[c][q];
+              r2 += diff[q] * diff[q];
+            }
+            R term, dsig, coef;
+            pair_terms<R>(r2, (R)dv, inv_sigma, inv_s2, term, dsig, coef);
+            tsum[c] += term;
+            dsum[c] += dsig;
+            cnt += 1;
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+              const R gq = coef * diff[q];
+              gi[q] += gq;
+              g[c][q] -= gq;
+            }
           }
         }
       }
-      wave_totals_lane63<D, R>(gi);
-      if (lane == 63)
+      // 16-lane row sums (row shifts 1, 2, 4, 8 leave each row's total in
+      // its lane 15), one step at a time across the D values so no DPP read
+      // waits on the add just before it
 #pragma unroll
-        for (int q = 0; q < D; ++q) s_row[w][r][q] = gi[q];
+      for (int q = 0; q < D; ++q) gi[q] += dpp_step<0x111, 0xf>(gi[q]);
+#pragma unroll
+      for (int q = 0; q < D; ++q) gi[q] += dpp_step<0x112, 0xf>(gi[q]);
+#pragma unroll
+      for (int q = 0; q < D; ++q) gi[q] += dpp_step<0x114, 0xf>(gi[q]);
+#pragma unroll
+      for (int q = 0; q < D; ++q) gi[q] += dpp_step<0x118, 0xf>(gi[q]);
+      if constexpr (NP == 1) {
+        // lane 63 gains lane 47 (row 2's total), then lane 31 (by then rows
+        // 0 and 1's total); rows 0 and 1 may pick up other values, which no
+        // one reads
+#pragma unroll
+        for (int q = 0; q < D; ++q) gi[q] += dpp_step<0x142, 0xf>(gi[q]);   // row_bcast:15
+#pragma unroll
+        for (int q = 0; q < D; ++q) gi[q] += dpp_step<0x143, 0xf>(gi[q]);   // row_bcast:31
+        if (lane == 63)
+#pragma unroll
+          for (int q = 0; q < D; ++q) s_row[w][r][0][q] = gi[q];
+      } else {
+        if ((lane & 15) == 15)
+#pragma unroll
+          for (int q = 0; q < D; ++q) s_row[w][r][lane >> 4][q] = gi[q];
+      }
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < rows * D; e += kThreads) {
+  for (int e = threadIdx.x; e < rows * D; e += NL) {
     const int r = e / D, q = e % D;
     double s = 0.0;
 #pragma unroll
-    for (int ww = 0; ww < kThreads / 64; ++ww) s += (double)s_row[ww][r][q];
+    for (int ww = 0; ww < NW; ++ww)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) s += (double)s_row[ww][r][k][q];
     a.prow[(tile * kTR + r) * D + q] = s;
   }
+  double tot[4] = {0.0, 0.0, (double)cnt, (double)bad};
 #pragma unroll
-  for (int q = 0; q < D; ++q) a.pcol[(tile * kTC + threadIdx.x) * D + q] = (double)g[q];
-  double tot[4] = {(double)tsum, (double)dsum, (double)cnt, (double)bad};
+  for (int c = 0; c < C; ++c) {
+#pragma unroll
+    for (int q = 0; q < D; ++q) a.pcol[(tile * kTC + jl[c]) * D + q] = (double)g[c][q];
+    tot[0] += (double)tsum[c];
+    tot[1] += (double)dsum[c];
+  }
   block_sum_n(tot, sh);
   if (threadIdx.x == 0)
     for (int k = 0; k < 4; ++k) a.ptile[tile * 4 + k] = tot[k];
@@ -312,8 +365,16 @@ static Pieces pieces(int64_t n, int d, int64_t& ntiles, int& nb) {
 
 template <int D>
 static void launch(const Args& a, int prec, hipStream_t s) {
-  if (prec == HAWKES_MIXED) k_bmds_tiles<D, true><<<(unsigned)a.ntiles, kThreads, 0, s>>>(a);
-  else k_bmds_tiles<D, false><<<(unsigned)a.ntiles, kThreads, 0, s>>>(a);
+  // wide lanes need enough tiles to fill the chip with fewer, longer waves
+  const bool wide = a.ntiles >= kWideTiles;
+  const unsigned nt = (unsigned)a.ntiles;
+  if (prec == HAWKES_MIXED) {
+    if (wide) k_bmds_tiles<D, true, kColsMixed><<<nt, TileShape<kColsMixed>::kLanes, 0, s>>>(a);
+    else k_bmds_tiles<D, true, 1><<<nt, TileShape<1>::kLanes, 0, s>>>(a);
+  } else {
+    if (wide) k_bmds_tiles<D, false, kColsFp64><<<nt, TileShape<kColsFp64>::kLanes, 0, s>>>(a);
+    else k_bmds_tiles<D, false, 1><<<nt, TileShape<1>::kLanes, 0, s>>>(a);
+  }
   k_bmds_final<<<1, kFinalThreads, 0, s>>>(a, D);
   if (a.grad_x) k_bmds_reduce<D><<<(a.n + 255) / 256, 256, 0, s>>>(a);
 }

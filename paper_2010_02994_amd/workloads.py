@@ -223,29 +223,67 @@ def bmds_case(seed: int, n: int, d: int, missing: float = 0.0, sigma: float = 0.
     countries and delta is the distance between the country centres (the
     air-traffic matrix is country by country), with same-country pairs
     unobserved.  `missing` marks a further random fraction unobserved."""
+    from scipy.spatial.distance import cdist
     rng = np.random.default_rng(seed)
     if groups > 0:
         centres = 2.0 * rng.standard_normal((groups, d))
         g = rng.integers(0, groups, size=n)
         z = centres[g] + 0.05 * rng.standard_normal((n, d))
-        base = np.linalg.norm(centres[g][:, None, :] - centres[g][None, :, :], axis=-1)
+        delta = cdist(centres, centres)[g][:, g]
     else:
         z = rng.standard_normal((n, d))
-        base = np.linalg.norm(z[:, None, :] - z[None, :, :], axis=-1)
-    noise = sigma * rng.standard_normal((n, n))
+        delta = cdist(z, z)
+    # symmetric folded noise: the strict lower triangle's draws mirrored
+    noise = rng.standard_normal((n, n))
+    noise *= sigma
     noise = np.tril(noise, -1)
-    noise = noise + noise.T
-    delta = np.abs(base + noise)
+    noise += noise.T
+    delta += noise
+    del noise
+    np.abs(delta, out=delta)
     if groups > 0:
         delta[g[:, None] == g[None, :]] = np.nan
     if missing > 0:
         m = np.tril(rng.uniform(size=(n, n)) < missing, -1)
-        m = m | m.T
+        m |= m.T
         delta[m] = np.nan
+        del m
     np.fill_diagonal(delta, np.nan)
     x = z + 0.1 * rng.standard_normal((n, d))
     return BmdsCase(f"bmds_s{seed}_n{n}_d{d}", np.ascontiguousarray(x), np.ascontiguousarray(delta), float(sigma),
                     seed)
+
+
+def bmds_case_device(seed: int, n: int, d: int, missing: float = 0.0, sigma: float = 0.3, groups: int = 0,
+                     device="cuda:0"):
+    """The recipe of `bmds_case` drawn with torch's seeded generator on
+    `device`, for sizes whose N x N matrix is slow to build on the host.
+    Returns (x, delta) as float64 device tensors and sigma."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    f64 = dict(generator=g, device=device, dtype=torch.float64)
+    if groups > 0:
+        centres = 2.0 * torch.randn((groups, d), **f64)
+        grp = torch.randint(0, groups, (n,), generator=g, device=device)
+        z = centres[grp] + 0.05 * torch.randn((n, d), **f64)
+        delta = torch.cdist(centres, centres)[grp][:, grp].contiguous()
+    else:
+        z = torch.randn((n, d), **f64)
+        delta = torch.cdist(z, z)
+    noise = torch.randn((n, n), **f64).tril_(-1)
+    delta.add_(sigma * (noise + noise.T)).abs_()
+    del noise
+    if groups > 0:
+        delta[grp[:, None] == grp[None, :]] = float("nan")
+    if missing > 0:
+        m = (torch.rand((n, n), generator=g, device=device, dtype=torch.float64) < missing).tril_(-1)
+        m |= m.T.clone()
+        delta[m] = float("nan")
+        del m
+    delta.fill_diagonal_(float("nan"))
+    x = z + 0.1 * torch.randn((n, d), **f64)
+    return x.contiguous(), delta, float(sigma)
 
 
 def flu_case(seed: int = 1004, n: int = 4733, d: int = 6, groups: int = 64, years: float = 12.0):
@@ -255,12 +293,23 @@ def flu_case(seed: int = 1004, n: int = 4733, d: int = 6, groups: int = 64, year
     dissimilarities of `bmds_case`, case times uniform over the span (sorted,
     no ties).  Returns (Workload with the Hawkes inputs, BmdsCase)."""
     c = bmds_case(seed, n, d, groups=groups)
+    return _flu_workload(seed, n, d, groups, years, c.x.copy()), c
+
+
+def _flu_workload(seed, n, d, groups, years, x):
     rng = np.random.default_rng(seed + 1)
     t = np.sort(rng.uniform(0.0, 365.0 * years, size=n))
     assert np.all(np.diff(t) > 0)
     # (mu0, tau_x, tau_t, theta, omega, h): background kernel wide in the
     # latent space and half a year in time, self-excitation within a country
     params = np.array([0.5, 1.0, 180.0, 0.5, 0.01, 0.2])
-    wl = Workload(f"flu_n{n}_d{d}_{groups}countries", c.x.copy(), t, params, seed=seed)
-    return wl, c
+    return Workload(f"flu_n{n}_d{d}_{groups}countries", np.ascontiguousarray(x), t, params, seed=seed)
+
+
+def flu_case_device(seed: int = 1004, n: int = 4733, d: int = 6, groups: int = 64, years: float = 12.0,
+                    device="cuda:0"):
+    """`flu_case` with the dissimilarities drawn on the device
+    (`bmds_case_device`).  Returns (Workload, delta tensor, sigma)."""
+    x, delta, sigma = bmds_case_device(seed, n, d, groups=groups, device=device)
+    return _flu_workload(seed, n, d, groups, years, x.cpu().numpy()), delta, sigma
 

@@ -59,3 +59,31 @@ def test_bmds_deterministic():
     a = _gpu(c, "mixed")
     b = _gpu(c, "mixed")
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+_big = {}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bmds_many_tiles_matches_oracle(prec):
+    """N = 12,000 (over 4,096 tiles, so several columns per lane)."""
+    import torch
+    from paper_2010_02994_amd import api
+    if "case" not in _big:
+        x, dl, sigma = W.bmds_case_device(9, 12000, 6, missing=0.05)
+        _big["case"] = (x, dl, sigma)
+        _big["ref"] = oracle.bmds(x.cpu().numpy(), dl.cpu().numpy(), sigma)
+    x, dl, sigma = _big["case"]
+    st, ll, ds, M, gx_ref = _big["ref"]
+    assert st == 0
+    say(f"case bmds n=12000 d=6 prec={prec}")
+    out4, gxd = api.bmds(x, dl, sigma, prec=prec)
+    torch.cuda.synchronize()
+    o, gx = out4.cpu().numpy(), gxd.cpu().numpy()
+    e_ll = abs(o[0] - ll) / abs(ll)
+    e_ds = abs(o[1] - ds) / max(abs(ds), M / sigma)
+    e_gx = np.linalg.norm(gx - gx_ref) / np.linalg.norm(gx_ref)
+    say(f"  err ll {e_ll:.2e} dsigma {e_ds:.2e} gx {e_gx:.2e}")
+    t = TOL[prec]
+    assert o[3] == 0 and o[2] == M
+    assert e_ll <= t["ll"] and e_ds <= t["ds"] and e_gx <= t["gx"]
