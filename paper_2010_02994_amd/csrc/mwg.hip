@@ -194,30 +194,6 @@ __global__ void __launch_bounds__(kBlock) k_mwg_rows(Step s) {
   }
 }
 
-// One workgroup: scan of the per-block counts, then the listed rows in index order.
-__global__ void __launch_bounds__(kListThreads) k_mwg_list(Step s) {
-  __shared__ int s_scan[kListThreads];
-  const int tid = threadIdx.x;
-  const int per = (s.nrb + kListThreads - 1) / kListThreads;
-  const int lo = min(s.nrb, tid * per), hi = min(s.nrb, lo + per);
-  int cnt = 0;
-  for (int b = lo; b < hi; ++b) cnt += s.bcount[b];
-  s_scan[tid] = cnt;
-  __syncthreads();
-  for (int off = 1; off < kListThreads; off <<= 1) {
-    const int v = tid >= off ? s_scan[tid - off] : 0;
-    __syncthreads();
-    s_scan[tid] += v;
-    __syncthreads();
-  }
-  int pos = s_scan[tid] - cnt;
-  for (int b = lo; b < hi; ++b) {
-    const int c = s.bcount[b];
-    for (int k = 0; k < c; ++k) s.list[pos++] = s.stage[(int64_t)b * kBlock + k];
-  }
-  if (tid == kListThreads - 1) s.state[1] = s_scan[kListThreads - 1];
-}
-
 // Partner segments per listed row: kSeg, or more when few rows are listed so
 // that the tasks still spread over the grid (never more partials than the
 // workspace holds: kSeg per event).
@@ -230,16 +206,52 @@ __device__ __forceinline__ int segs_for(int cnt, int n) {
 
 // Exact rows, split into (row, partner segment) tasks over a fixed grid: sums
 // of the row's pair terms against one segment of partners, every event at its
-// proposed place; a moved row sits at its proposed location.
+// proposed place; a moved row sits at its proposed location.  The listed rows
+// in index order come from k_mwg_rows' per-block counts and staged rows: every
+// workgroup scans the counts (each thread over a chunk of consecutive blocks)
+// and finds its tasks' rows from the scan; workgroup 0 also writes the list
+// and its length, which the later kernels read.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_mwg_exact(Step s) {
   __shared__ double sh[2 * kBlock];
-  const int cnt = s.state[1];
+  __shared__ int s_scan[kBlock];
+  const int tid = threadIdx.x;
+  const int per = (s.nrb + kBlock - 1) / kBlock;
+  const int lo = min(s.nrb, tid * per), hi = min(s.nrb, lo + per);
+  int own = 0;
+  for (int b = lo; b < hi; ++b) own += s.bcount[b];
+  s_scan[tid] = own;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int v = tid >= off ? s_scan[tid - off] : 0;
+    __syncthreads();
+    s_scan[tid] += v;
+    __syncthreads();
+  }
+  const int cnt = s_scan[kBlock - 1];
+  if (blockIdx.x == 0) {
+    int pos = s_scan[tid] - own;
+    for (int b = lo; b < hi; ++b) {
+      const int c = s.bcount[b];
+      for (int k = 0; k < c; ++k) s.list[pos++] = s.stage[(int64_t)b * kBlock + k];
+    }
+    if (tid == 0) s.state[1] = cnt;
+  }
   const int segs = segs_for(cnt, s.n);
   const int seg = (s.n + segs - 1) / segs;
   for (int64_t task = blockIdx.x; task < (int64_t)cnt * segs; task += gridDim.x) {
     const int e = (int)(task / segs), sg = (int)(task % segs);
-    const int r = s.list[e];
+    // listed row e: the first chunk whose inclusive count exceeds e, then the
+    // block inside it
+    int c0 = 0, c1 = kBlock - 1;
+    while (c0 < c1) {
+      const int mid = (c0 + c1) >> 1;
+      if (s_scan[mid] > e) c1 = mid; else c0 = mid + 1;
+    }
+    int rr = e - (c0 > 0 ? s_scan[c0 - 1] : 0);
+    int rb = c0 * per;
+    for (int cb = s.bcount[rb]; rr >= cb; cb = s.bcount[rb]) { rr -= cb; ++rb; }
+    const int r = s.stage[(int64_t)rb * kBlock + rr];
     const int rpos = s.flag[r] == 2 ? find_moved(s.idx, s.nmove, r) : -1;
     double xr[D];
 #pragma unroll
@@ -410,7 +422,6 @@ static Pieces pieces(int64_t n) {
 template <int D>
 static void launch(const Step& s, hipStream_t st) {
   k_mwg_rows<D><<<s.nrb, kBlock, 0, st>>>(s);
-  k_mwg_list<<<1, kListThreads, 0, st>>>(s);
   k_mwg_exact<D><<<kExactGrid, kBlock, 0, st>>>(s);
   k_mwg_decide<<<1, kListThreads, 0, st>>>(s, D);
   k_mwg_apply<D><<<s.nrb, kBlock, 0, st>>>(s);

@@ -259,7 +259,7 @@ bool admit_and_launch(hawkes_server* S) {
       if (st == HAWKES_OK && hipEventRecord(b.done, b.stream) != hipSuccess) st = HAWKES_EDEVICE;
       if (st != HAWKES_OK) {
         // the launch failed: fail this batch's requests, keep serving others
-        hipStreamSynchronize(b.stream);
+        (void)hipStreamSynchronize(b.stream);
         for (auto* r : take) finish(S, r, st, nullptr);
         b.busy = false;
         b.reqs.clear();
@@ -292,18 +292,18 @@ void worker_loop(hawkes_server* S) {
 void free_server(hawkes_server* S) {
   for (auto& b : S->batches) {
     if (!S->simulate) {
-      if (b.stream) hipStreamDestroy(b.stream);
-      if (b.done) hipEventDestroy(b.done);
-      if (b.dev_desc) hipFree(b.dev_desc);
-      if (b.dev_out) hipFree(b.dev_out);
-      if (b.host_desc) hipHostFree(b.host_desc);
-      if (b.host_out) hipHostFree(b.host_out);
+      if (b.stream) (void)hipStreamDestroy(b.stream);
+      if (b.done) (void)hipEventDestroy(b.done);
+      if (b.dev_desc) (void)hipFree(b.dev_desc);
+      if (b.dev_out) (void)hipFree(b.dev_out);
+      if (b.host_desc) (void)hipHostFree(b.host_desc);
+      if (b.host_out) (void)hipHostFree(b.host_out);
     }
   }
   if (!S->simulate) {
     for (auto& ds : S->datasets)
-      if (ds.t) hipFree(ds.t);
-    if (S->arena_base) hipFree(S->arena_base);
+      if (ds.t) (void)hipFree(ds.t);
+    if (S->arena_base) (void)hipFree(S->arena_base);
   }
   for (auto& kv : S->by_ticket) delete kv.second;
   delete S;
