@@ -298,6 +298,27 @@ size_t hawkes_serve_footprint(int64_t n, int d, int prec);
  * EINVAL: max_slots outside [1, 1024] or budget below 1 MiB; EDEVICE: HIP failure. */
 int hawkes_serve_create(size_t hbm_budget_bytes, int max_slots, int flags, hawkes_server_t** out);
 
+/* A source of device memory for a server, e.g. a framework's caching
+ * allocator, so the server's memory shows in the framework's accounting.
+ * alloc returns `bytes` of device memory aligned to 256 bytes (NULL on
+ * failure); free takes back a pointer alloc returned.  Both are called only
+ * from hawkes_serve_create_with, hawkes_serve_register and
+ * hawkes_serve_destroy, on the calling thread (never by the scheduler). */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} hawkes_allocator_t;
+
+/* As hawkes_serve_create, with every device buffer of the server (the arena,
+ * the per-stream descriptor and result slots, the registered datasets' times)
+ * taken from `alloc` and given back to it by hawkes_serve_destroy; the pinned
+ * host staging still comes from hipHostMalloc.  alloc == NULL: hipMalloc.  A
+ * buffer that comes back misaligned is returned and counts as a failure
+ * (EDEVICE); alloc with a NULL function: EINVAL. */
+int hawkes_serve_create_with(const hawkes_allocator_t* alloc, size_t hbm_budget_bytes, int max_slots, int flags,
+                             hawkes_server_t** out);
+
 /* Register a dataset's event times (device, n, sorted) for dimension d; the
  * server keeps its own device copy.  Returns the dataset id. */
 int hawkes_serve_register(hawkes_server_t* s, const double* t /* device */, int64_t n, int d, int32_t* dataset_id);

@@ -82,6 +82,14 @@ class ServeStats(ctypes.Structure):
                 ("arena_free_bytes", ctypes.c_uint64)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class HawkesAllocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
 SERVE_SIMULATE = 0x100
 BOUND_NONE, BOUND_BOX, BOUND_DISC = 0, 1, 2
 
@@ -91,6 +99,8 @@ def _bind_serve(L):
     L.hawkes_serve_footprint.argtypes = [i64, ci, ci]
     L.hawkes_serve_footprint.restype = ctypes.c_size_t
     L.hawkes_serve_create.argtypes = [ctypes.c_size_t, ci, ci, ctypes.POINTER(vp)]
+    L.hawkes_serve_create_with.argtypes = [ctypes.POINTER(HawkesAllocator), ctypes.c_size_t, ci, ci,
+                                           ctypes.POINTER(vp)]
     L.hawkes_serve_register.argtypes = [vp, vp, i64, ci, ctypes.POINTER(ctypes.c_int32)]
     L.hawkes_serve_submit.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(HawkesParams), ci, vp,
                                       ctypes.POINTER(u64)]
@@ -98,8 +108,8 @@ def _bind_serve(L):
     L.hawkes_serve_wait.argtypes = [vp, u64, ctypes.POINTER(ServeResult), i64]
     L.hawkes_serve_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
     L.hawkes_serve_destroy.argtypes = [vp]
-    for f in (L.hawkes_serve_create, L.hawkes_serve_register, L.hawkes_serve_submit, L.hawkes_serve_poll,
-              L.hawkes_serve_wait, L.hawkes_serve_stats, L.hawkes_serve_destroy):
+    for f in (L.hawkes_serve_create, L.hawkes_serve_create_with, L.hawkes_serve_register, L.hawkes_serve_submit,
+              L.hawkes_serve_poll, L.hawkes_serve_wait, L.hawkes_serve_stats, L.hawkes_serve_destroy):
         f.restype = ci
 
 

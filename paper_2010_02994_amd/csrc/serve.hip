@@ -123,6 +123,7 @@ struct hawkes_server {
   size_t budget = 0;
   int max_slots = 0;
   bool simulate = false;
+  hawkes_allocator_t alloc{};     // device memory source (alloc.alloc == NULL: hipMalloc)
   char* arena_base = nullptr;
   hawkes::Arena arena;
   std::vector<hawkes::Dataset> datasets;
@@ -140,6 +141,28 @@ struct hawkes_server {
 
 namespace hawkes {
 namespace {
+
+// Device memory of the server: the caller's allocator when given, else hipMalloc.
+// Buffers must come back aligned to 256 bytes.
+void* dev_alloc(hawkes_server* S, size_t bytes) {
+  void* p = nullptr;
+  if (S->alloc.alloc) {
+    p = S->alloc.alloc(bytes, S->alloc.ctx);
+    if (p && (reinterpret_cast<uintptr_t>(p) & 255u) != 0) {
+      S->alloc.free(p, S->alloc.ctx);
+      p = nullptr;
+    }
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  return p;
+}
+
+void dev_free(hawkes_server* S, void* p) {
+  if (!p) return;
+  if (S->alloc.alloc) S->alloc.free(p, S->alloc.ctx);
+  else (void)hipFree(p);
+}
 
 size_t footprint(int64_t n, int d, int prec) {
   const size_t ws = hawkes_workspace_bytes(n, d, prec);
@@ -294,16 +317,16 @@ void free_server(hawkes_server* S) {
     if (!S->simulate) {
       if (b.stream) (void)hipStreamDestroy(b.stream);
       if (b.done) (void)hipEventDestroy(b.done);
-      if (b.dev_desc) (void)hipFree(b.dev_desc);
-      if (b.dev_out) (void)hipFree(b.dev_out);
+      dev_free(S, b.dev_desc);
+      dev_free(S, b.dev_out);
       if (b.host_desc) (void)hipHostFree(b.host_desc);
       if (b.host_out) (void)hipHostFree(b.host_out);
     }
   }
   if (!S->simulate) {
     for (auto& ds : S->datasets)
-      if (ds.t) (void)hipFree(ds.t);
-    if (S->arena_base) (void)hipFree(S->arena_base);
+      dev_free(S, ds.t);
+    dev_free(S, S->arena_base);
   }
   for (auto& kv : S->by_ticket) delete kv.second;
   delete S;
@@ -317,22 +340,30 @@ extern "C" {
 size_t hawkes_serve_footprint(int64_t n, int d, int prec) { return hawkes::footprint(n, d, prec); }
 
 int hawkes_serve_create(size_t hbm_budget_bytes, int max_slots, int flags, hawkes_server_t** out) {
+  return hawkes_serve_create_with(nullptr, hbm_budget_bytes, max_slots, flags, out);
+}
+
+int hawkes_serve_create_with(const hawkes_allocator_t* alloc, size_t hbm_budget_bytes, int max_slots, int flags,
+                             hawkes_server_t** out) {
   using namespace hawkes;
   if (!out || max_slots < 1 || max_slots > 1024 || hbm_budget_bytes < (1u << 20)) return HAWKES_EINVAL;
+  if (alloc && (!alloc->alloc || !alloc->free)) return HAWKES_EINVAL;
   const int streams = std::max(1, std::min(8, flags & 0xff ? (flags & 0xff) : 2));
   hawkes_server* S = new hawkes_server;
+  if (alloc) S->alloc = *alloc;
   S->budget = hbm_budget_bytes;
   S->max_slots = max_slots;
   S->simulate = (flags & HAWKES_SERVE_SIMULATE) != 0;
   S->arena.reset(hbm_budget_bytes);
   S->batches.resize(streams);
   if (!S->simulate) {
-    bool ok = hipMalloc(&S->arena_base, hbm_budget_bytes) == hipSuccess;
+    S->arena_base = static_cast<char*>(dev_alloc(S, hbm_budget_bytes));
+    bool ok = S->arena_base != nullptr;
     for (auto& b : S->batches) {
       ok = ok && hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) == hipSuccess;
       ok = ok && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess;
-      ok = ok && hipMalloc(&b.dev_desc, sizeof(ReqDesc) * max_slots) == hipSuccess;
-      ok = ok && hipMalloc(&b.dev_out, sizeof(double) * 8 * max_slots) == hipSuccess;
+      ok = ok && (b.dev_desc = static_cast<ReqDesc*>(dev_alloc(S, sizeof(ReqDesc) * max_slots))) != nullptr;
+      ok = ok && (b.dev_out = static_cast<double*>(dev_alloc(S, sizeof(double) * 8 * max_slots))) != nullptr;
       ok = ok && hipHostMalloc(&b.host_desc, sizeof(ReqDesc) * max_slots, hipHostMallocDefault) == hipSuccess;
       ok = ok && hipHostMalloc(&b.host_out, sizeof(double) * 8 * max_slots, hipHostMallocDefault) == hipSuccess;
     }
@@ -360,9 +391,10 @@ int hawkes_serve_register(hawkes_server_t* S, const double* t, int64_t n, int d,
   ds.n = n;
   ds.d = d;
   if (!S->simulate) {
-    if (hipMalloc(&ds.t, sizeof(double) * n) != hipSuccess) return HAWKES_EDEVICE;
+    ds.t = static_cast<double*>(dev_alloc(S, sizeof(double) * n));
+    if (!ds.t) return HAWKES_EDEVICE;
     if (hipMemcpy(ds.t, t, sizeof(double) * n, hipMemcpyDeviceToDevice) != hipSuccess) {
-      hipFree(ds.t);
+      dev_free(S, ds.t);
       return HAWKES_EDEVICE;
     }
   } else {
@@ -370,7 +402,7 @@ int hawkes_serve_register(hawkes_server_t* S, const double* t, int64_t n, int d,
   }
   std::lock_guard<std::mutex> lk(S->mu);
   if (S->stop) {
-    if (!S->simulate) hipFree(ds.t);
+    if (!S->simulate) dev_free(S, ds.t);
     return HAWKES_ESTATE;
   }
   S->datasets.push_back(ds);

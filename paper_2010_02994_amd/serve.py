@@ -14,13 +14,44 @@ from ._lib import HawkesError, ServeResult, ServeStats
 from .api import _prec, params_struct
 
 
+class _TorchMemory:
+    """Device memory for a server from PyTorch's caching allocator: each block
+    is a uint8 tensor kept alive until the server gives the pointer back."""
+
+    def __init__(self, device):
+        self.device = device
+        self.blocks: dict[int, object] = {}
+        self._alloc = _lib.ALLOC_FN(self._on_alloc)
+        self._free = _lib.FREE_FN(self._on_free)
+        self.spec = _lib.HawkesAllocator(self._alloc, self._free, None)
+
+    def _on_alloc(self, nbytes, ctx):
+        try:
+            import torch
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except Exception:   # out of memory: the server reports the failure
+            return None
+        self.blocks[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _on_free(self, ptr, ctx):
+        self.blocks.pop(int(ptr), None)
+
+
 class Server:
     def __init__(self, hbm_budget_bytes: int = 8 << 30, max_slots: int = 64, streams: int = 2,
-                 simulate: bool = False):
+                 simulate: bool = False, torch_memory: bool = False, device="cuda:0"):
+        """torch_memory: take the server's device buffers from PyTorch's
+        caching allocator (hawkes_serve_create_with) instead of hipMalloc."""
         self._L = _lib.lib()
         self._h = ctypes.c_void_p()
         flags = (streams & 0xFF) | (_lib.SERVE_SIMULATE if simulate else 0)
-        st = self._L.hawkes_serve_create(int(hbm_budget_bytes), int(max_slots), flags, ctypes.byref(self._h))
+        self._mem = _TorchMemory(device) if torch_memory else None
+        if self._mem is not None:
+            st = self._L.hawkes_serve_create_with(ctypes.byref(self._mem.spec), int(hbm_budget_bytes),
+                                                  int(max_slots), flags, ctypes.byref(self._h))
+        else:
+            st = self._L.hawkes_serve_create(int(hbm_budget_bytes), int(max_slots), flags, ctypes.byref(self._h))
         if st != _lib.OK:
             raise HawkesError(st, "hawkes_serve_create")
         self.simulate = simulate
@@ -86,6 +117,10 @@ class Server:
         if st != _lib.OK:
             raise HawkesError(st, "hawkes_serve_stats")
         return {k: getattr(s, k) for k, _ in ServeStats._fields_}
+
+    def device_blocks(self) -> int:
+        """Device buffers the server holds from PyTorch (torch_memory only)."""
+        return len(self._mem.blocks) if self._mem is not None else 0
 
     def close(self):
         if self._h:

@@ -136,3 +136,27 @@ def test_open_loop_short_run():
     say(f"  open loop: {out}")
     assert out["requests"] == 200 and out["errors"] == 0 and out["unfinished"] == 0
     assert out["p50_ms"] > 0 and out["p99_ms"] >= out["p50_ms"]
+
+
+def test_server_on_torch_memory(data):
+    """A server whose arena, result slots and dataset copies come from
+    PyTorch's caching allocator gives the direct call's results bitwise, holds
+    its blocks while open (torch accounts for the arena) and gives every block
+    back when closed."""
+    budget = 1 << 30
+    before = torch.cuda.memory_allocated()
+    with Server(hbm_budget_bytes=budget, max_slots=16, streams=2, torch_memory=True) as s:
+        ids = [s.register(d[2], 2) for d in data[:3]]
+        say("case serve on torch memory")
+        assert s.device_blocks() == 1 + 2 * 2 + 3
+        assert torch.cuda.memory_allocated() - before >= budget
+        outs = [torch.full_like(data[k][1], float("nan")) for k in range(3)]
+        res = [s.wait(s.submit(ids[k], data[k][1], data[k][0].params, prec="mixed", grad_x=outs[k]), 60)
+               for k in range(3)]
+        torch.cuda.synchronize()
+        for k, r in enumerate(res):
+            w, x, t = data[k]
+            ll, gx, gp = api.grad(x, t, w.params, prec="mixed")
+            assert r["status"] == 0 and r["loglik"] == ll and np.array_equal(np.array(r["grad_params"]), gp)
+            assert np.array_equal(outs[k].cpu().numpy(), gx.cpu().numpy())
+    assert s.device_blocks() == 0

@@ -116,3 +116,15 @@ def test_batches_are_homogeneous_in_the_gradient_flag():
         res = [s.wait(tk, 10) for tk in tks]
         assert all(r["status"] == 0 for r in res)
         assert s.stats()["batches_launched"] >= 2
+
+
+def test_create_with_incomplete_allocator_is_rejected():
+    """An allocator without both functions is refused on the host (no device
+    call is made)."""
+    import ctypes
+    from paper_2010_02994_amd import _lib
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    spec = _lib.HawkesAllocator()   # both function pointers NULL
+    st = L.hawkes_serve_create_with(ctypes.byref(spec), 1 << 30, 4, _lib.SERVE_SIMULATE, ctypes.byref(h))
+    assert st == _lib.EINVAL and not h.value
