@@ -211,26 +211,40 @@ bool harvest(hawkes_server* S) {
   return any;
 }
 
+// Size band of a request: N within a factor of 4.  A batch completes when its
+// largest request does, so mixing sizes would make small requests wait for a
+// large one; banding keeps each batch's requests of similar duration, and the
+// large ones run beside the small ones on other streams instead.
+int size_band(int64_t n) {
+  int b = 0;
+  while (n >= 4) { n >>= 2; ++b; }
+  return b;
+}
+
 // Admit from the FIFO into free batch slots and launch.  The head request
 // decides the batch's class (D, precision, with or without a location
-// gradient); later requests of another class wait for a later batch.  The
-// class fixes which rate-pass variant runs, so a request's arithmetic is the
-// same alone, in any batch and through the direct calls.  A head request that does not fit in memory blocks
-// admission until memory frees up (no overtaking by smaller requests of its
-// class), which keeps admission fair.
+// gradient, size band); later requests of another class wait for a later
+// batch.  D, precision and the gradient flag fix which kernels run, so a
+// request's arithmetic is the same alone, in any batch and through the direct
+// calls.  A head request that does not fit in memory blocks admission until
+// memory frees up (no overtaking by smaller requests of its class), which
+// keeps admission fair.
 bool admit_and_launch(hawkes_server* S) {
   bool any = false;
   for (auto& b : S->batches) {
     if (b.busy || S->pending.empty()) continue;
     std::vector<Request*> take;
-    int cls_d = -1, cls_p = -1;
+    int cls_d = -1, cls_p = -1, cls_b = -1;
     bool cls_g = false;
     for (auto it = S->pending.begin(); it != S->pending.end();) {
       Request* r = *it;
       const Dataset& ds = S->datasets[r->ds];
       if (S->active >= S->max_slots) break;
-      if (cls_d < 0) { cls_d = ds.d; cls_p = r->prec; cls_g = r->grad_x != nullptr; }
-      if (ds.d != cls_d || r->prec != cls_p || (r->grad_x != nullptr) != cls_g) { ++it; continue; }
+      if (cls_d < 0) { cls_d = ds.d; cls_p = r->prec; cls_g = r->grad_x != nullptr; cls_b = size_band(ds.n); }
+      if (ds.d != cls_d || r->prec != cls_p || (r->grad_x != nullptr) != cls_g || size_band(ds.n) != cls_b) {
+        ++it;
+        continue;
+      }
       size_t off;
       if (!S->arena.alloc(r->foot, &off)) {
         if (take.empty()) { cls_d = -1; }
