@@ -43,6 +43,12 @@ constexpr int kFixGrid = 256;            // workgroups per request in the fix-up
 constexpr int kFixSeg = 16;             // partner segments per flagged row in the fix-up kernels
 constexpr int kEvBlock = 256;           // events per block of the per-event kernels
 // float32 pair passes: steps whose exps are issued together (rate, gradient)
+// Waves per SIMD the mixed passes are compiled for: the register budget
+// (512 / waves per lane) must hold the rows' state, which grows with D, or
+// the kernel spills to scratch.  The set values apply at D <= 2; wider
+// records take fewer waves.
+constexpr int rate_waves(int d, bool ru) { return ru && d >= 2 ? 4 : HK_RATE_WAVES_PER_EU; }
+constexpr int grad_waves(int d) { return d <= 2 ? HK_GRAD_WAVES_PER_EU : d <= 4 ? 5 : d <= 6 ? 4 : 3; }
 constexpr int kRateExpSteps = HK_RATE_EXP_STEPS;
 constexpr int kGradExpSteps = HK_GRAD_EXP_STEPS;
 

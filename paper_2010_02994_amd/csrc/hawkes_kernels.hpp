@@ -649,7 +649,7 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
 // pass keeps K, J, V, W (four row sums, one column sum) and the gradient pass
 // forms the two moments' contributions to the parameter gradient instead.
 template <int D, bool RU>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HK_RATE_WAVES_PER_EU))) k_pass1_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(rate_waves(D, RU)))) k_pass1_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
   using Rec = typename Traits<D, true>::Rec;
   using Real = float;
   using ColT = float;
@@ -816,7 +816,7 @@ __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const ty
 }
 
 template <int D>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(HK_GRAD_WAVES_PER_EU))) k_pass2_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(grad_waves(D)))) k_pass2_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
   using Rec = typename Traits<D, true>::Rec;
   using Real = float;
   using ColT = float;
