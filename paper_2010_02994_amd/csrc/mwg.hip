@@ -50,7 +50,7 @@ struct Step {
   // workspace
   double* new_a;        // n each
   double* new_b;
-  double* dlog;
+  double* dlog;         // incremental rows: log-rate change; listed rows: old log-rate
   int* flag;            // 0 incremental, 1 recompute exactly, 2 moved
   double* bpart;        // nrb: per row block, sum of dlog over its incremental rows
   int* bcount;          // nrb: rows of the block needing an exact recompute
@@ -173,7 +173,8 @@ __global__ void __launch_bounds__(kBlock) k_mwg_rows(Step s) {
       if (fl == 0) dl = log1p((s.m.mu0 * da + s.m.theta * db) / lam);
     }
     s.flag[i] = fl;
-    s.dlog[i] = dl;
+    // listed rows: their old log-rate, for the exact change formed later
+    s.dlog[i] = fl == 0 ? dl : s.terms[(int64_t)i * 4 + 2];
   }
   const double bs = block_sum(dl, sh);
   // stage the rows needing an exact recompute, in index order
@@ -279,65 +280,76 @@ __global__ void __launch_bounds__(kBlock) k_mwg_exact(Step s) {
   }
 }
 
-// One workgroup: checks the moved list, merges the exact rows' segments in a
-// fixed order, sums the log-rate changes in a fixed order, decides.  (A
-// separate launch: a device-wide fence in every workgroup of the exact kernel
-// would write back the L2 of each die, which costs more than the launch.)
-__global__ void __launch_bounds__(kListThreads) k_mwg_decide(Step s, int D) {
-  __shared__ double sh[kListThreads];
+// Decision and update in one launch.  Every workgroup checks the moved block,
+// merges the listed rows' segments and sums the log-rate changes in the same
+// fixed order, so all of them reach the same total and the same decision;
+// each then updates its own rows on accept, and workgroup 0 reports.  The
+// listed rows' old log-rates come from k_mwg_rows' copy (a workgroup updating
+// its rows' cached terms must not change what another one reads).  (A
+// device-wide fence in every workgroup of the exact kernel, to decide in its
+// last workgroup instead, would write back the L2 of each die, which costs
+// more than a launch.)
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_mwg_settle(Step s) {
+  __shared__ double sh[kBlock];
+  __shared__ double s_na[kBlock], s_nb[kBlock], s_dl[kBlock];
+  __shared__ int s_own[kBlock];
   __shared__ int s_bad;
-  if (threadIdx.x == 0) s_bad = 0;
+  const int tid = threadIdx.x;
+  const int base = blockIdx.x * kBlock;
+  s_own[tid] = 0;
+  if (tid == 0) s_bad = 0;
   __syncthreads();
-  for (int k = threadIdx.x; k < s.nmove; k += kListThreads) {
+  for (int k = tid; k < s.nmove; k += kBlock) {
     const int64_t j = s.idx[k];
     bool bad = j < 0 || j >= s.n || (k > 0 && s.idx[k - 1] >= j);
+#pragma unroll
     for (int q = 0; q < D; ++q) bad = bad || !isfinite(s.xnew[(int64_t)k * D + q]);
     if (bad) atomicOr(&s_bad, 1);
   }
   const int cnt = s.state[1];
   const int segs = segs_for(cnt, s.n);
-  // one wave per listed row: its lanes add strided segments, a butterfly
-  // combines them (the same fixed order every time), lane 0 keeps the row's
-  // log-rate change in its running sum
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // G lanes per listed row (segs / 4, at most a wave): they add strided
+  // segments, a butterfly within the group combines them (the same fixed
+  // order every time), and the group's first lane keeps the row's log-rate
+  // change in its running sum.  Many listed rows (G small) run side by side.
+  const int G = min(64, segs / 4);
+  const int grp = tid / G, gl = tid % G;
   double acc = 0.0;
-  for (int e = wave; e < cnt; e += kListThreads / 64) {
+  for (int e = grp; e < cnt; e += kBlock / G) {
     double a = 0.0, b = 0.0;
-    for (int sg = lane; sg < segs; sg += 64) {
+    for (int sg = gl; sg < segs; sg += G) {
       a += s.part[((int64_t)e * segs + sg) * 2 + 0];
       b += s.part[((int64_t)e * segs + sg) * 2 + 1];
     }
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int o = G / 2; o > 0; o >>= 1) {
       a += __shfl_xor(a, o);
       b += __shfl_xor(b, o);
     }
-    if (lane == 0) {
+    if (gl == 0) {
       const int r = s.list[e];
-      const double dl = log(s.m.mu0 * a + s.m.theta * b) - s.terms[(int64_t)r * 4 + 2];
-      s.new_a[r] = a;
-      s.new_b[r] = b;
-      s.dlog[r] = dl;
+      const double dl = log(s.m.mu0 * a + s.m.theta * b) - s.dlog[r];
       acc += dl;
+      if (r >= base && r < base + kBlock) {
+        s_na[r - base] = a;
+        s_nb[r - base] = b;
+        s_dl[r - base] = dl;
+        s_own[r - base] = 1;
+      }
     }
   }
-  for (int b = threadIdx.x; b < s.nrb; b += kListThreads) acc += s.bpart[b];
-  const double tot = block_sum(acc, sh);
-  if (threadIdx.x == 0) {
-    const bool bad = s_bad != 0;
-    const bool accept = !bad && tot > *s.thresh;
+  for (int b = tid; b < s.nrb; b += kBlock) acc += s.bpart[b];
+  const double tot = block_sum(acc, sh);   // also orders the LDS writes above
+  const bool bad = s_bad != 0;
+  const bool accept = !bad && tot > *s.thresh;
+  if (blockIdx.x == 0 && tid == 0) {
     s.out3[0] = bad ? NAN : tot;
     s.out3[1] = accept ? 1.0 : 0.0;
     s.out3[2] = bad ? (double)HAWKES_EDATA : 0.0;
     s.state[0] = accept ? 1 : 0;
   }
-}
-
-// On accept: move the locations and refresh the cached terms of every row
-// that changed (untouched rows keep their bits).
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_mwg_apply(Step s) {
-  if (s.state[0] == 0) return;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (!accept) return;
+  const int i = base + tid;
   if (i < s.nmove) {
     const int64_t j = s.idx[i];
 #pragma unroll
@@ -345,12 +357,13 @@ __global__ void __launch_bounds__(kBlock) k_mwg_apply(Step s) {
   }
   if (i >= s.n) return;
   double* tp = s.terms + (int64_t)i * 4;
-  const double na = s.new_a[i], nb = s.new_b[i];
+  const bool own = s_own[tid] != 0;
+  const double na = own ? s_na[tid] : s.new_a[i], nb = own ? s_nb[tid] : s.new_b[i];
   if (s.flag[i] == 0 && na == tp[0] && nb == tp[1]) return;
   const double lam1 = s.m.mu0 * na + s.m.theta * nb;
   tp[0] = na;
   tp[1] = nb;
-  tp[2] = tp[2] + s.dlog[i];
+  tp[2] = tp[2] + (own ? s_dl[tid] : s.dlog[i]);
   tp[3] = s.m.theta * nb / lam1;
 }
 
@@ -423,8 +436,7 @@ template <int D>
 static void launch(const Step& s, hipStream_t st) {
   k_mwg_rows<D><<<s.nrb, kBlock, 0, st>>>(s);
   k_mwg_exact<D><<<kExactGrid, kBlock, 0, st>>>(s);
-  k_mwg_decide<<<1, kListThreads, 0, st>>>(s, D);
-  k_mwg_apply<D><<<s.nrb, kBlock, 0, st>>>(s);
+  k_mwg_settle<D><<<s.nrb, kBlock, 0, st>>>(s);
 }
 
 }  // namespace mwg
