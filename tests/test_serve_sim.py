@@ -128,3 +128,22 @@ def test_create_with_incomplete_allocator_is_rejected():
     spec = _lib.HawkesAllocator()   # both function pointers NULL
     st = L.hawkes_serve_create_with(ctypes.byref(spec), 1 << 30, 4, _lib.SERVE_SIMULATE, ctypes.byref(h))
     assert st == _lib.EINVAL and not h.value
+
+
+def test_batches_group_by_size_band():
+    """Requests of one class but N a factor of 20 apart go to different
+    batches (a batch ends with its largest request), each batch starting all
+    of its requests together."""
+    with Server(hbm_budget_bytes=8 << 30, max_slots=64, streams=1, simulate=True) as s:
+        big = s.register(1, 2, n=200000)
+        small = s.register(1, 2, n=2000)
+        large = s.register(1, 2, n=40000)
+        blocker = s.submit(big, 1, P)           # holds the only stream for ~40 ms
+        tks = [s.submit(small if k % 2 == 0 else large, 1, P) for k in range(8)]
+        assert s.wait(blocker, 10)["status"] == 0
+        res = [s.wait(tk, 10) for tk in tks]
+        assert all(r["status"] == 0 for r in res)
+        starts_small = {r["t_start_ns"] for r in res[0::2]}
+        starts_large = {r["t_start_ns"] for r in res[1::2]}
+        assert len(starts_small) == 1 and len(starts_large) == 1 and starts_small != starts_large
+        assert s.stats()["batches_launched"] == 3
