@@ -46,3 +46,37 @@ class HawkesLoglik(torch.autograd.Function):
 def hawkes_loglik(x: torch.Tensor, params: torch.Tensor, t: torch.Tensor, prec: str = "mixed") -> torch.Tensor:
     """Differentiable log-likelihood ell(x, params; t)."""
     return HawkesLoglik.apply(x, params, t, prec)
+
+
+class BmdsLoglik(torch.autograd.Function):
+    """Bayesian MDS log-likelihood of the latent locations (Sec. 2.2.3) with its
+    hand-written adjoint: one library call returns ell, d ell/d sigma and
+    d ell/d x.  With `hawkes_loglik` on the same x this gives the influenza
+    model's log density over the locations and its gradient (Sec. 3)."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, sigma: torch.Tensor, delta: torch.Tensor, prec: str = "fp64"):
+        """x: (N, D) device tensor; sigma: scalar tensor (> 0); delta: (N, N)
+        float64 device tensor (strict lower triangle read, NaN = unobserved).
+        Returns ell as a 0-d float64 tensor on x's device (no host sync)."""
+        x64 = x.detach().to(torch.float64).contiguous()
+        s = float(sigma.detach().reshape(()).item())
+        out4, gx = api.bmds(x64, delta.detach().to(torch.float64).contiguous(), s, prec=prec)
+        ctx.x_dtype = x.dtype
+        ctx.s_meta = (sigma.dtype, sigma.device, sigma.shape)
+        ctx.save_for_backward(gx, out4)
+        return out4[0].clone()
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, g: torch.Tensor):
+        gx, out4 = ctx.saved_tensors
+        dtype, device, shape = ctx.s_meta
+        gxo = (gx * g.to(gx.device)).to(ctx.x_dtype) if ctx.needs_input_grad[0] else None
+        gso = (out4[1].to(device) * g.to(device)).to(dtype).reshape(shape) if ctx.needs_input_grad[1] else None
+        return gxo, gso, None, None
+
+
+def bmds_loglik(x: torch.Tensor, sigma: torch.Tensor, delta: torch.Tensor, prec: str = "fp64") -> torch.Tensor:
+    """Differentiable MDS log-likelihood ell(x, sigma; delta)."""
+    return BmdsLoglik.apply(x, sigma, delta, prec)

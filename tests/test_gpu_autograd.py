@@ -105,3 +105,31 @@ def test_config3_finite_differences_and_oracle(c3, prec):
     tol_or = 1e-10 if prec == "fp64" else 1e-4
     assert e_fd_x <= tol_fd and e_fd_p <= tol_fd
     assert e_or_x <= tol_or and e_or_p <= tol_or
+
+
+def test_bmds_gradcheck_and_joint_backward():
+    """The MDS adjoint: torch.autograd.gradcheck in x and sigma (float64, small
+    N), and the influenza model's joint log density hawkes + mds backpropagates
+    the sum of the two library gradients."""
+    from paper_2010_02994_amd import api
+    from paper_2010_02994_amd.autograd import bmds_loglik
+    c = W.bmds_case(230, 24, 3, missing=0.2)
+    x = torch.tensor(c.x, device=DEV, requires_grad=True)
+    s = torch.tensor(c.sigma, dtype=torch.float64, device=DEV, requires_grad=True)
+    dl = torch.tensor(c.delta, device=DEV)
+    say("case bmds gradcheck")
+    assert torch.autograd.gradcheck(lambda xx, ss: bmds_loglik(xx, ss, dl, "fp64"), (x, s), eps=1e-6, atol=1e-6,
+                                    rtol=1e-5)
+    w, cf = W.flu_case(seed=231, n=400, d=6, groups=10, years=2.0)
+    say("case joint hawkes + mds backward")
+    for prec in ("fp64", "mixed"):
+        xj = torch.tensor(w.x, device=DEV, requires_grad=True)
+        t = torch.tensor(w.t, device=DEV)
+        dj = torch.tensor(cf.delta, device=DEV)
+        sj = torch.tensor(cf.sigma, dtype=torch.float64, device=DEV)
+        p = torch.tensor(w.params, dtype=torch.float64)
+        (hawkes_loglik(xj, p, t, prec) + bmds_loglik(xj, sj, dj, prec)).backward()
+        _, gh, _ = api.grad(xj.detach(), t, w.params, prec=prec)
+        _, gb = api.bmds(xj.detach(), dj, cf.sigma, prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(xj.grad, gh + gb), prec
