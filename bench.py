@@ -205,6 +205,11 @@ def main():
     path_work = pairs_u * (f1 + f2 + (e1 + e2) * FLOP_EQ_PER_EXP)
 
     mwg = mwg_bench(w, dev, args.mwg_steps) if args.mwg_steps > 0 else None
+    if mwg is not None:
+        # the same moves at the size of the paper's wildfire data (N = 2,925,
+        # same events per km^2 and day), for the per-state context
+        from paper_2010_02994_amd import workloads as _wl
+        mwg["n2925"] = mwg_bench(_wl.config2(n=2925, same_density=True), dev, args.mwg_steps)
     hmc = leapfrog_bench(dev, args.hmc_trajectories) if args.hmc_trajectories > 0 else None
     bmds = bmds_bench(dev, args.bmds_reps) if args.bmds_reps > 0 else None
 
@@ -253,6 +258,7 @@ def mwg_bench(w, dev, steps: int):
     t = torch.tensor(w.t, device=dev)
     out = {"workload": f"{w.name}: latent-disc location moves", "state": "fp64 per-event terms"}
     for block, n_steps in ((1, steps), (64, max(1, steps // 6))):
+        x.copy_(torch.tensor(w.x, device=dev))   # each block size starts from the workload's state
         terms, _ = api.event_terms(x, t, w.params, prec="fp64")
         idx = np.sort(np.stack([rng.choice(latent, size=block, replace=False) for _ in range(n_steps)]), axis=1)
         ang = rng.uniform(0, 2 * np.pi, idx.shape)

@@ -158,9 +158,10 @@ size_t hawkes_mwg_workspace_bytes(int64_t n);
  * (device, n x 4, from hawkes_event_terms with the same parameters, every
  * lambda_n > 0) is updated in place; on reject nothing changes.
  * out3 (device, 3 doubles) receives [Delta ell, accepted (0 or 1), status].
- * Rows whose rate the move cancels to below 2^-26 of the terms it is formed
- * from are recomputed exactly; other rows are updated incrementally, so after
- * many accepted moves a periodic hawkes_event_terms refresh bounds the drift.
+ * Rows whose rate, or either part of it (a or b), the move cancels to below
+ * 2^-16 of the terms it is formed from are recomputed exactly; other rows are
+ * updated incrementally, so after many accepted moves a periodic
+ * hawkes_event_terms refresh bounds the drift.
  * Enqueue only: no host synchronization.  Host-side argument errors return at
  * once; an invalid idx or non-finite x_new is reported in out3 (status
  * HAWKES_EDATA, Delta ell NaN, rejected).  Calls sharing a workspace must be

@@ -25,6 +25,7 @@ namespace hawkes {
 namespace mwg {
 
 constexpr int kBlock = 256;
+constexpr double kGuard = 0x1p-16; // incremental update kept only above this share of its terms
 constexpr int kSeg = 32;          // partner segments per exactly recomputed row (workspace per event)
 constexpr int kMaxSeg = 512;      // at most, when few rows are listed
 constexpr int kExactGrid = 512;   // workgroups of the exact-row kernel (grid-stride over tasks)
@@ -104,9 +105,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // Rows not moved: the change of (a_i, b_i) from the moved events' old and new
 // places, and its log-rate change, summed per block in a fixed order.  When the
-// change cancels most of the rate (the new rate is below 2^-26 of the terms it
-// was formed from) the row is listed for an exact recompute instead, so float64
-// cancellation never decides a move.  Moved rows are listed too.
+// change cancels most of the rate or of either part of it (the new value is
+// below 2^-16 of the terms it was formed from, so its rounding error could
+// exceed ~2^-37 of it) the row is listed for an exact recompute instead, so
+// float64 cancellation neither decides a move nor corrupts the cached parts.
+// Moved rows are listed too.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_mwg_rows(Step s) {
   __shared__ double s_old[kBlock][D];
@@ -167,7 +170,10 @@ __global__ void __launch_bounds__(kBlock) k_mwg_rows(Step s) {
       const double lam = s.m.mu0 * a + s.m.theta * b;
       const double lam1 = s.m.mu0 * na + s.m.theta * nb;
       const double formed_from = lam + s.m.mu0 * oa + s.m.theta * ob;
-      fl = lam1 > 0x1p-26 * formed_from ? 0 : 1;
+      const double fa = a + oa, fb = b + ob;   // magnitudes each part was formed from
+      const bool kept = lam1 > kGuard * formed_from && !(fa > 0.0 && !(na > kGuard * fa)) &&
+                        !(fb > 0.0 && !(nb > kGuard * fb));
+      fl = kept ? 0 : 1;
       s.new_a[i] = na;
       s.new_b[i] = nb;
       if (fl == 0) dl = log1p((s.m.mu0 * da + s.m.theta * db) / lam);

@@ -126,10 +126,13 @@ def config1(seed: int = 1001, snapshots: int = 20) -> Workload:
 C2_PARAMS = np.array([0.5, 1.0, 10.0, 0.3, 0.1, 2.0])
 
 
-def config2(seed: int = 1002, n: int = 50000) -> Workload:
+def config2(seed: int = 1002, n: int = 50000, same_density: bool = False) -> Workload:
+    """same_density: shrink the box (and the mixture) by sqrt(n / 50,000) so a
+    smaller n keeps the 50,000-event workload's events per km^2 and day."""
     rng = np.random.default_rng(seed)
-    x, t = _cluster_events(rng, n, 0.2, [(100, 100), (250, 350), (400, 150)], 40.0, 500.0,
-                           3650.0, 2.0, 10.0)
+    s = float(np.sqrt(n / 50000.0)) if same_density else 1.0
+    x, t = _cluster_events(rng, n, 0.2, [(100 * s, 100 * s), (250 * s, 350 * s), (400 * s, 150 * s)], 40.0 * s,
+                           500.0 * s, 3650.0, 2.0, 10.0)
     obs = x.copy()
     n_disc = int(round(0.3 * n))
     idx = rng.choice(n, size=n_disc, replace=False)
@@ -140,8 +143,8 @@ def config2(seed: int = 1002, n: int = 50000) -> Workload:
     lat = obs.copy()
     lat[idx, 0] += r[idx] * np.sqrt(u) * np.cos(2 * np.pi * v)
     lat[idx, 1] += r[idx] * np.sqrt(u) * np.sin(2 * np.pi * v)
-    return Workload(f"c2_n{n}_d2_disc", np.ascontiguousarray(lat), t, C2_PARAMS.copy(),
-                    observed=obs, radius=r, seed=seed)
+    name = f"c2_n{n}_d2_disc" + (f"_box{500 * s:.0f}km" if same_density else "")
+    return Workload(name, np.ascontiguousarray(lat), t, C2_PARAMS.copy(), observed=obs, radius=r, seed=seed)
 
 
 C3_PARAMS = np.array([0.5, 1.0, 10.0, 0.3, 0.5, 0.05])

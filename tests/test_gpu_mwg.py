@@ -217,3 +217,34 @@ def test_loglik_reweight():
         assert o[0] == pytest.approx(ll, rel=1e-12)
         assert abs(o[1] - gm) <= 1e-10 * max(abs(gm), w.n)
         assert abs(o[2] - gt) <= 1e-10 * max(abs(gt), w.n)
+
+
+@pytest.mark.parametrize("n,block", [(2925, 64), (2925, 200), (6000, 64)])
+def test_mwg_large_blocks_match_oracle(n, block):
+    """Blocks of many moved events on the wildfire-like workload (latent disc
+    locations, same events per km^2 and day as N = 50,000): Delta ell against
+    the oracle, reject and accept, and the cached terms after accepting."""
+    import torch
+    from paper_2010_02994_amd import api
+    w = W.config2(n=n, same_density=True)
+    rng = np.random.default_rng(n + block)
+    latent = np.flatnonzero(w.radius > 0)
+    idx = np.sort(rng.choice(latent, size=block, replace=False))
+    ang = rng.uniform(0, 2 * np.pi, block)
+    rad = w.radius[idx] * np.sqrt(rng.uniform(size=block))
+    xn = w.observed[idx] + np.stack([rad * np.cos(ang), rad * np.sin(ang)], axis=-1)
+    ref_delta, x1 = oracle.mwg_delta(w.x, w.t, w.params, list(idx), xn)
+    say(f"case mwg n={n} block={block}: ref delta {ref_delta:.10g}")
+    xd, td, terms = _state(w)
+    idx_d, xn_d = _dev(idx.astype(np.int64)), _dev(xn)
+    out = api.mwg_step(xd, td, w.params, terms, idx_d, xn_d, _dev([math.inf]))
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    say(f"  gpu delta {o[0]:.10g} status {o[2]}")
+    assert o[2] == 0 and o[1] == 0
+    assert abs(o[0] - ref_delta) <= 1e-9 * max(1.0, abs(ref_delta))
+    out = api.mwg_step(xd, td, w.params, terms, idx_d, xn_d, _dev([-math.inf]))
+    torch.cuda.synchronize()
+    assert out.cpu().numpy()[1] == 1
+    assert np.array_equal(xd.cpu().numpy(), x1)
+    _check_terms(terms.cpu().numpy(), oracle.event_terms(x1, w.t, w.params), "fp64", w.params, "large block")
