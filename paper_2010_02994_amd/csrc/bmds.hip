@@ -364,25 +364,27 @@ static Pieces pieces(int64_t n, int d, int64_t& ntiles, int& nb) {
 }
 
 template <int D>
-static void launch(const Args& a, int prec, hipStream_t s) {
-  // wide lanes need enough tiles to fill the chip with fewer, longer waves
-  const bool wide = a.ntiles >= kWideTiles;
-  const unsigned nt = (unsigned)a.ntiles;
-  if (prec == HAWKES_MIXED) {
-    if (wide) k_bmds_tiles<D, true, kColsMixed><<<nt, TileShape<kColsMixed>::kLanes, 0, s>>>(a);
-    else k_bmds_tiles<D, true, 1><<<nt, TileShape<1>::kLanes, 0, s>>>(a);
-  } else {
-    if (wide) k_bmds_tiles<D, false, kColsFp64><<<nt, TileShape<kColsFp64>::kLanes, 0, s>>>(a);
-    else k_bmds_tiles<D, false, 1><<<nt, TileShape<1>::kLanes, 0, s>>>(a);
+static void launch(const Args& a, int prec, hipStream_t s, int phase) {
+  if (phase != 2) {
+    // wide lanes need enough tiles to fill the chip with fewer, longer waves
+    const bool wide = a.ntiles >= kWideTiles;
+    const unsigned nt = (unsigned)a.ntiles;
+    if (prec == HAWKES_MIXED) {
+      if (wide) k_bmds_tiles<D, true, kColsMixed><<<nt, TileShape<kColsMixed>::kLanes, 0, s>>>(a);
+      else k_bmds_tiles<D, true, 1><<<nt, TileShape<1>::kLanes, 0, s>>>(a);
+    } else {
+      if (wide) k_bmds_tiles<D, false, kColsFp64><<<nt, TileShape<kColsFp64>::kLanes, 0, s>>>(a);
+      else k_bmds_tiles<D, false, 1><<<nt, TileShape<1>::kLanes, 0, s>>>(a);
+    }
+    k_bmds_final<<<1, kFinalThreads, 0, s>>>(a, D);
   }
-  k_bmds_final<<<1, kFinalThreads, 0, s>>>(a, D);
-  if (a.grad_x) k_bmds_reduce<D><<<(a.n + 255) / 256, 256, 0, s>>>(a);
+  if (phase != 1 && a.grad_x) k_bmds_reduce<D><<<(a.n + 255) / 256, 256, 0, s>>>(a);
 }
 
 }  // namespace bmds
 
 int bmds_enqueue(const double* x, const double* delta, int64_t n, int d, double sigma, int prec, void* ws,
-                 size_t ws_bytes, hipStream_t s, double* out4, double* grad_x, bool accumulate) {
+                 size_t ws_bytes, hipStream_t s, double* out4, double* grad_x, bool accumulate, int phase) {
   using namespace bmds;
   if (!x || !delta || !ws || !out4) return HAWKES_EINVAL;
   if (prec != HAWKES_FP64 && prec != HAWKES_MIXED) return HAWKES_EINVAL;
@@ -406,14 +408,14 @@ int bmds_enqueue(const double* x, const double* delta, int64_t n, int d, double 
   a.accumulate = accumulate ? 1 : 0;
   (void)hipGetLastError();
   switch (d) {
-    case 1: launch<1>(a, prec, s); break;
-    case 2: launch<2>(a, prec, s); break;
-    case 3: launch<3>(a, prec, s); break;
-    case 4: launch<4>(a, prec, s); break;
-    case 5: launch<5>(a, prec, s); break;
-    case 6: launch<6>(a, prec, s); break;
-    case 7: launch<7>(a, prec, s); break;
-    case 8: launch<8>(a, prec, s); break;
+    case 1: launch<1>(a, prec, s, phase); break;
+    case 2: launch<2>(a, prec, s, phase); break;
+    case 3: launch<3>(a, prec, s, phase); break;
+    case 4: launch<4>(a, prec, s, phase); break;
+    case 5: launch<5>(a, prec, s, phase); break;
+    case 6: launch<6>(a, prec, s, phase); break;
+    case 7: launch<7>(a, prec, s, phase); break;
+    case 8: launch<8>(a, prec, s, phase); break;
   }
   return hipGetLastError() == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
 }

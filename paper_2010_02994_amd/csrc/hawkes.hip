@@ -236,11 +236,6 @@ static inline void mark(hipStream_t s, int stage) {
 // kernels (fix1, final1, fix2) run on the side
 // stream while pass 2 runs on the caller's stream: pass 2 reads nothing they
 // write, and k_reduce2, which reads both, waits for the side chain.
-struct Fork {
-  hipStream_t side;
-  hipEvent_t ready, done;
-};
-
 // Forks are held exclusively while a call enqueues (an event re-recorded by
 // another thread between record and wait would order the wrong work) and
 // returned afterwards; the stream work they ordered needs nothing more.  One
@@ -286,6 +281,8 @@ static ForkPool& fork_pool() {
   static ForkPool* p = new ForkPool();   // never destroyed: streams outlive static destructors
   return *p;
 }
+Fork* fork_take(int dev, bool allow_create) { return fork_pool().take(dev, allow_create); }
+void fork_give(int dev, Fork* f) { fork_pool().give(dev, f); }
 
 // The phases over every request of a batch (all with the same D and
 // precision).  reqs: device array of descriptors; totals: grid sizes.

@@ -38,9 +38,22 @@ int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const Batc
 // grad_x is not null, the gradient pass) with no host synchronization.
 int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
               size_t ws_bytes, void* stream, double* out8, double* grad_x, double* terms = nullptr);
+// A side stream and two events, from a per-device pool kept for the life of
+// the process.  A fork is held exclusively while a call enqueues and given
+// back afterwards.  allow_create = false (the stream is being captured into a
+// graph): only a pooled fork is handed out, else nullptr.
+struct Fork {
+  hipStream_t side;
+  hipEvent_t ready, done;
+};
+Fork* fork_take(int dev, bool allow_create);
+void fork_give(int dev, Fork* f);
+
 // Enqueue one Bayesian MDS evaluation; accumulate: grad_x += its location
-// gradient instead of grad_x = it.
+// gradient instead of grad_x = it.  phase 0: everything on s; phase 1: the
+// pair pass and the scalars only; phase 2: only the per-event gradient
+// reduction (after phase 1's work, with the same arguments).
 int bmds_enqueue(const double* x, const double* delta, int64_t n, int d, double sigma, int prec, void* ws,
-                 size_t ws_bytes, hipStream_t s, double* out4, double* grad_x, bool accumulate);
+                 size_t ws_bytes, hipStream_t s, double* out4, double* grad_x, bool accumulate, int phase = 0);
 
 }  // namespace hawkes

@@ -171,13 +171,47 @@ struct MdsTerm {
   double* out4;
 };
 
-// grad_x = the location gradient of the potential's log density at x.
+// grad_x = the location gradient of the potential's log density at x.  With
+// the MDS term, its pair pass runs on a side stream beside the Hawkes
+// evaluation (both only read x), and its gradient is added on the caller's
+// stream once both are done.
 static int gradient(double* x, const double* t, int64_t n, int d, const hawkes_params_t* prm, int prec, void* ws,
                     size_t ws_bytes, hipStream_t s, double* grad_x, double* out8, const MdsTerm* mds) {
-  int st = run_async(x, t, n, d, prm, prec, ws, ws_bytes, s, out8, grad_x);
-  if (st == HAWKES_OK && mds)
-    st = bmds_enqueue(x, mds->delta, n, d, mds->sigma, prec & ~HAWKES_CULL, mds->ws, mds->ws_bytes, s, mds->out4,
-                      grad_x, true);
+  const int mprec = prec & ~HAWKES_CULL;
+  Fork* fk = nullptr;
+  int dev = -1;
+  if (mds && hipGetDevice(&dev) == hipSuccess) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+    fk = fork_take(dev, !capturing);
+  }
+  int st = HAWKES_OK;
+  if (fk) {
+    if (hipEventRecord(fk->ready, s) != hipSuccess || hipStreamWaitEvent(fk->side, fk->ready, 0) != hipSuccess)
+      st = HAWKES_EDEVICE;
+    if (st == HAWKES_OK)
+      st = bmds_enqueue(x, mds->delta, n, d, mds->sigma, mprec, mds->ws, mds->ws_bytes, fk->side, mds->out4,
+                        grad_x, true, 1);
+    if (st == HAWKES_OK && hipEventRecord(fk->done, fk->side) != hipSuccess) st = HAWKES_EDEVICE;
+  }
+  if (st == HAWKES_OK) st = run_async(x, t, n, d, prm, prec, ws, ws_bytes, s, out8, grad_x);
+  if (st == HAWKES_OK && mds) {
+    if (fk) {
+      st = hipStreamWaitEvent(s, fk->done, 0) == hipSuccess ? HAWKES_OK : HAWKES_EDEVICE;
+      if (st == HAWKES_OK)
+        st = bmds_enqueue(x, mds->delta, n, d, mds->sigma, mprec, mds->ws, mds->ws_bytes, s, mds->out4, grad_x,
+                          true, 2);
+    } else {
+      st = bmds_enqueue(x, mds->delta, n, d, mds->sigma, mprec, mds->ws, mds->ws_bytes, s, mds->out4, grad_x,
+                        true, 0);
+    }
+  }
+  if (fk) {
+    // an early error leaves the side stream's work unjoined: join it so the
+    // fork goes back to the pool with nothing pending against this call
+    if (st != HAWKES_OK) (void)hipStreamWaitEvent(s, fk->done, 0);
+    fork_give(dev, fk);
+  }
   return st;
 }
 

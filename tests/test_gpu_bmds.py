@@ -65,18 +65,19 @@ _big = {}
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_bmds_many_tiles_matches_oracle(prec):
+@pytest.mark.parametrize("d", [6, 2])
+def test_bmds_many_tiles_matches_oracle(prec, d):
     """N = 12,000 (over 4,096 tiles, so several columns per lane)."""
     import torch
     from paper_2010_02994_amd import api
-    if "case" not in _big:
-        x, dl, sigma = W.bmds_case_device(9, 12000, 6, missing=0.05)
-        _big["case"] = (x, dl, sigma)
-        _big["ref"] = oracle.bmds(x.cpu().numpy(), dl.cpu().numpy(), sigma)
+    if _big.get("d") != d:
+        _big.clear()
+        x, dl, sigma = W.bmds_case_device(9 + d, 12000, d, missing=0.05)
+        _big.update(d=d, case=(x, dl, sigma), ref=oracle.bmds(x.cpu().numpy(), dl.cpu().numpy(), sigma))
     x, dl, sigma = _big["case"]
     st, ll, ds, M, gx_ref = _big["ref"]
     assert st == 0
-    say(f"case bmds n=12000 d=6 prec={prec}")
+    say(f"case bmds n=12000 d={d} prec={prec}")
     out4, gxd = api.bmds(x, dl, sigma, prec=prec)
     torch.cuda.synchronize()
     o, gx = out4.cpu().numpy(), gxd.cpu().numpy()

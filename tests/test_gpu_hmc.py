@@ -196,3 +196,50 @@ def test_leapfrog_bmds_gradient_is_the_sum_of_the_single_calls():
         torch.cuda.synchronize()
         assert torch.equal(g, gh + gb), prec
         assert torch.equal(out8, o8) and torch.equal(out4, o4), prec
+
+
+def test_leapfrog_bmds_graph_replay_matches_eager():
+    """The joint trajectory (its MDS pair pass on a side stream beside each
+    Hawkes evaluation) captured once in a HIP graph and replayed three times,
+    with eager work between the replays, equals three eager trajectories bit
+    for bit."""
+    import torch
+    from paper_2010_02994_amd import api
+    w, c = W.flu_case(seed=109, n=600, d=6, groups=12, years=3.0)
+    rng = np.random.default_rng(109)
+    p0 = rng.standard_normal(w.x.shape)
+    t, dl = _dev(w.t), _dev(c.delta)
+    say("case leapfrog+bmds graph replay")
+    for prec in ("mixed", "fp64"):
+        x, p = _dev(w.x), _dev(p0)
+        g, _, _ = api.leapfrog_bmds(x, p, t, w.params, dl, c.sigma, 0.002, 1, prec=prec)
+        x0, p0d, g0 = x.clone(), p.clone(), g.clone()
+        eager = []
+        for _ in range(3):
+            g, o8, o4 = api.leapfrog_bmds(x, p, t, w.params, dl, c.sigma, 0.002, 4, prec=prec, grad_x=g,
+                                          have_grad=True)
+            torch.cuda.synchronize()
+            eager.append(tuple(v.cpu().numpy() for v in (x, p, g, o8, o4)))
+        xs, ps, gs = x0.clone(), p0d.clone(), g0.clone()
+        o8g = torch.empty(8, dtype=torch.float64, device="cuda:0")
+        o4g = torch.empty(4, dtype=torch.float64, device="cuda:0")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):   # warm the capture stream's workspaces outside the capture
+            api.leapfrog_bmds(xs.clone(), ps.clone(), t, w.params, dl, c.sigma, 0.002, 1, prec=prec,
+                              grad_x=gs.clone(), have_grad=True, out8=o8g, out4=o4g)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            api.leapfrog_bmds(xs, ps, t, w.params, dl, c.sigma, 0.002, 4, prec=prec, grad_x=gs, have_grad=True,
+                              out8=o8g, out4=o4g)
+        xs.copy_(x0); ps.copy_(p0d); gs.copy_(g0)
+        torch.cuda.synchronize()
+        for k in range(3):
+            graph.replay()
+            torch.cuda.synchronize()
+            got = tuple(v.cpu().numpy() for v in (xs, ps, gs, o8g, o4g))
+            _ = (xs * 2).sum().item()   # unrelated eager work between replays
+            for a, b in zip(got, eager[k]):
+                assert np.array_equal(a, b), (prec, k)
