@@ -294,10 +294,19 @@ def mwg_bench(w, dev, steps: int):
         el = time.perf_counter() - t0
         o = outs.cpu().numpy()
         timed = n_steps - warm
+        # drift of the incrementally updated terms against a fresh evaluation
+        fresh, _ = api.event_terms(x, t, w.params, prec="fp64")
+        tc, tf = terms.cpu().numpy(), fresh.cpu().numpy()
+        lam = w.params[0] * tf[:, 0] + w.params[3] * tf[:, 1]
+        drift_ab = float(np.max((w.params[0] * np.abs(tc[:, 0] - tf[:, 0]) + w.params[3] * np.abs(tc[:, 1] - tf[:, 1]))
+                                / lam))
+        drift_log = float(np.max(np.abs(tc[:, 2] - tf[:, 2])))
         out[f"block{block}"] = {"steps": timed, "us_per_step": el / max(timed, 1) * 1e6,
                                 "steps_per_s": timed / el if el > 0 else None,
                                 "pair_terms_per_step": block * (w.n - 1) * 2,
-                                "accept_rate": float(o[:, 1].mean()), "bad_status": int((o[:, 2] != 0).sum())}
+                                "accept_rate": float(o[:, 1].mean()), "bad_status": int((o[:, 2] != 0).sum()),
+                                "accepted": int(o[:, 1].sum()),
+                                "terms_drift": {"rate_rel_max": drift_ab, "log_rate_abs_max": drift_log}}
     x.copy_(torch.tensor(w.x, device=dev))
     return out
 
