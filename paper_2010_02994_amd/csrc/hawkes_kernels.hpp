@@ -1344,7 +1344,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce2(const ReqDesc* __restri
   const int sub = threadIdx.x & 3;
   const int i = (blockIdx.x - rq.blk_ev) * kEvBlock + (threadIdx.x >> 2);
   if (uni(glb(rq.status)[kStData]) != 0) return;
-  if (MIX && !kp.ru1 && blockIdx.x == rq.blk_ev) {
+  if (MIX && !kp.ru1 && (int)blockIdx.x == rq.blk_ev) {
     // the background moments' terms of d ell/d tau_x and d ell/d tau_t, from
     // the gradient pass's item sums in item order: sum over pairs of
     // w r'^2 = sum_n c_bg R_n / (tau_x^3 lambda_n) and w dt'^2 tau_x / tau_t =
