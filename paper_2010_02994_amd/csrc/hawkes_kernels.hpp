@@ -69,14 +69,15 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // Exact culling: every pair of the band's rows with this column tile lies
 // further apart in time than kp.cull_dt, so both pair terms are exactly zero
 // in this pass's arithmetic.  Records are time-sorted, so the band's first row
-// and the tile's last column bound every pair's time difference.
-template <int D, bool MIX, typename RecPtr>
-__device__ __forceinline__ bool tile_culled(RecPtr rec, int row_base, int tile, const KParams& kp) {
+// (t_row0, read once per work item) and the tile's last column (read from the
+// tile's records already staged in LDS) bound every pair's time difference.
+template <int D, bool MIX, typename Real, typename Rec>
+__device__ __forceinline__ bool tile_culled(Real t_row0, const Rec* tile_recs, int tile, const KParams& kp) {
   if (!kp.cull) return false;
-  const int last = min(kp.n - 1, tile * kTile + kTile - 1);
+  const int last = min(kp.n - 1, tile * kTile + kTile - 1) - tile * kTile;
   bool c;
-  if constexpr (MIX) c = (float)rec[row_base].v[D] - (float)rec[last].v[D] > kp.cull_dtf;
-  else c = (double)rec[row_base].v[D] - (double)rec[last].v[D] > kp.cull_dt;
+  if constexpr (MIX) c = (float)t_row0 - (float)tile_recs[last].v[D] > kp.cull_dtf;
+  else c = (double)t_row0 - (double)tile_recs[last].v[D] > kp.cull_dt;
   return uni(c ? 1 : 0) != 0;
 }
 
@@ -332,6 +333,7 @@ __global__ void __launch_bounds__(kThreads) k_pass1(const ReqDesc* __restrict__ 
   const int tile1 = min(tile0 + kp.L, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
   const int first_min = uni(first[row_base]);
+  const auto t_row0 = rec[row_base].v[D];   // the band's first row (culling)
 
   Pass1Rows<D, false> S;
 #pragma unroll
@@ -367,7 +369,7 @@ __global__ void __launch_bounds__(kThreads) k_pass1(const ReqDesc* __restrict__ 
       pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
     }
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
-    if (tile_culled<D, MIX>(rec, row_base, tile, kp)) {
+    if (tile_culled<D, MIX>(t_row0, &s_rec[buf][0], tile, kp)) {
       // nothing to add: the tile's column sums stay zero
     } else if (full) {
       pass1_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
@@ -485,6 +487,7 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ 
   const int tile1 = min(tile0 + kp.L, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
   const int first_min = uni(first[row_base]);
+  const auto t_row0 = rec[row_base].v[D];   // the band's first row (culling)
 
   Pass2Rows<D, false> S;
 #pragma unroll
@@ -520,7 +523,7 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ 
       pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
     }
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
-    if (tile_culled<D, MIX>(rec, row_base, tile, kp)) {
+    if (tile_culled<D, MIX>(t_row0, &s_rec[buf][0], tile, kp)) {
       // nothing to add: the tile's column sums stay zero
     } else if (full) {
       pass2_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
@@ -675,6 +678,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(r
   const int tile1 = min(tile0 + kp.L, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
   const int first_min = uni(first[row_base]);
+  const auto t_row0 = rec[row_base].v[D];   // the band's first row (culling)
 
   Pass1Rows<D, true> S;
 #pragma unroll
@@ -707,7 +711,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(r
       pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
     }
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
-    if (tile_culled<D, true>(rec, row_base, tile, kp)) {
+    if (tile_culled<D, true>(t_row0, &s_rec[buf][0], tile, kp)) {
       // the tile adds exactly zero: its column sums are zero
 #pragma unroll
       for (int q = 0; q < NQ; ++q) s_acc[buf][wave][q][lane] = 0.f;
@@ -842,6 +846,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(g
   const int tile1 = min(tile0 + kp.L, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
   const int first_min = uni(first[row_base]);
+  const auto t_row0 = rec[row_base].v[D];   // the band's first row (culling)
 
   Pass2Rows<D, true> S;
   S.mom[0] = S.mom[1] = 0.f;
@@ -876,7 +881,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(g
       pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
     }
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
-    if (tile_culled<D, true>(rec, row_base, tile, kp)) {
+    if (tile_culled<D, true>(t_row0, &s_rec[buf][0], tile, kp)) {
       // the tile adds exactly zero: its column sums are zero
 #pragma unroll
       for (int q = 0; q < NQ; ++q) s_acc[buf][wave][q][lane] = 0.f;
