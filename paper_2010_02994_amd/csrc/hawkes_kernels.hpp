@@ -41,7 +41,46 @@ template <int D> struct Traits<D, false> {
 // ------------------------------------------------------------------ helpers
 
 __device__ __forceinline__ float exp_pair(float z) { return __builtin_amdgcn_exp2f(z); }
-__device__ __forceinline__ double exp_pair(double z) { return exp(z); }
+
+// Float64 exp of the pair passes, by Tang's table-driven method (P. T. P. Tang,
+// ACM Trans. Math. Softw. 15(2), 1989) with 64 table entries tab[j] = 2^(j/64)
+// held in LDS: z = (64 m + j) ln2/64 + r with |r| <= ln2/128, and
+// exp(z) = 2^m tab[j] (1 + p(r)), p the degree-5 Taylor polynomial of expm1
+// (truncation below r^6/720 < 4e-17 relative).  The reduction subtracts k ln2/64
+// in two fused steps (ln2/64 split into a double and its remainder), so r is
+// exact to ~1e-18 for every |z| < 1e4.  ldexp rounds once, also into the
+// subnormal range; arguments below -746, where exp is 0, return exactly 0.
+#ifndef HK_FP64_EXP_TABLE
+#define HK_FP64_EXP_TABLE 1
+#endif
+__device__ __forceinline__ double exp_tab(double z, const double* __restrict__ tab) {
+#if HK_FP64_EXP_TABLE
+  constexpr double kInvStep = 92.33248261689366;        // 64 / ln2
+  constexpr double kStepHi = 0x1.62e42fefa39efp-7;       // ln2 / 64, rounded
+  constexpr double kStepLo = 0x1.abc9e3b39803fp-62;      // ln2 / 64 - kStepHi
+  const double kf = __builtin_rint(z * kInvStep);
+  const int k = (int)kf;
+  double r = __builtin_fma(-kf, kStepHi, z);
+  r = __builtin_fma(-kf, kStepLo, r);
+  double p = __builtin_fma(r, 1.0 / 120.0, 1.0 / 24.0);
+  p = __builtin_fma(r, p, 1.0 / 6.0);
+  p = __builtin_fma(r, p, 0.5);
+  p = __builtin_fma(r, p, 1.0);
+  p = r * p;
+  const double tj = tab[k & 63];
+  const double v = __builtin_ldexp(__builtin_fma(tj, p, tj), k >> 6);
+  return z < -746.0 ? 0.0 : v;
+#else
+  (void)tab;
+  return exp(z);
+#endif
+}
+
+// Fills the 64-entry table of exp_tab; the caller synchronizes the workgroup
+// before the first use.
+__device__ __forceinline__ void fill_exp_table(double* tab) {
+  if (threadIdx.x < 64) tab[threadIdx.x] = exp2((double)threadIdx.x * (1.0 / 64.0));
+}
 
 __device__ __forceinline__ double block_max_256(double v, double* sh) {
   const int tid = threadIdx.x;
@@ -252,7 +291,7 @@ struct Pass1Rows {
 template <int D, bool MIX, bool MASK>
 __device__ __forceinline__ void pass1_tile(Pass1Rows<D, MIX>& S, const typename Traits<D, MIX>::Rec* __restrict__ cols,
                                            typename Traits<D, MIX>::ColT* __restrict__ acc_w, int tile_base,
-                                           const KParams& kp) {
+                                           const KParams& kp, const double* __restrict__ tab) {
   using Real = typename Traits<D, MIX>::Real;
   constexpr int R = kRowsPerLane;
   const int lane = threadIdx.x & 63;
@@ -278,8 +317,8 @@ __device__ __forceinline__ void pass1_tile(Pass1Rows<D, MIX>& S, const typename 
       const Real v = ct * (dt * dt);
       const Real ys = cg * r2;
       const Real ws = cw * dt;
-      Real eb = exp_pair((sh - u) - v);
-      Real es = exp_pair((sh - ys) - ws);
+      Real eb = exp_tab((sh - u) - v, tab);
+      Real es = exp_tab((sh - ys) - ws, tab);
       if (MASK) {
         const bool act = (tile_base + c) < S.first[r];
         eb = act ? eb : Real(0);
@@ -316,6 +355,8 @@ __global__ void __launch_bounds__(kThreads) k_pass1(const ReqDesc* __restrict__ 
   constexpr int NQ = 3;
   __shared__ Rec s_rec[2][kTile];
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
+  __shared__ double s_exptab[64];   // 2^(j/64) for exp_tab
+  fill_exp_table(s_exptab);
   const int rid = find_req(reqs, nreq, blockIdx.x, 0);
   const ReqDesc& rq = reqs[rid];
   if (uni(glb(rq.status)[kStData]) != 0) return;
@@ -372,9 +413,9 @@ __global__ void __launch_bounds__(kThreads) k_pass1(const ReqDesc* __restrict__ 
     if (tile_culled<D, MIX>(t_row0, &s_rec[buf][0], tile, kp)) {
       // nothing to add: the tile's column sums stay zero
     } else if (full) {
-      pass1_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+      pass1_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp, s_exptab);
     } else {
-      pass1_tile<D, MIX, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+      pass1_tile<D, MIX, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp, s_exptab);
     }
 
   }
@@ -416,7 +457,7 @@ struct Pass2Rows {
 template <int D, bool MIX, bool MASK>
 __device__ __forceinline__ void pass2_tile(Pass2Rows<D, MIX>& S, const typename Traits<D, MIX>::Rec* __restrict__ cols,
                                            typename Traits<D, MIX>::ColT* __restrict__ acc_w, int tile_base,
-                                           const KParams& kp) {
+                                           const KParams& kp, const double* __restrict__ tab) {
   using Real = typename Traits<D, MIX>::Real;
   constexpr int R = kRowsPerLane;
   const int lane = threadIdx.x & 63;
@@ -442,8 +483,8 @@ __device__ __forceinline__ void pass2_tile(Pass2Rows<D, MIX>& S, const typename 
       const Real dt = S.t[r] - col.v[D];
       const Real zb = (sh - cb * r2) - ct * (dt * dt);
       const Real zs = (sh - cg * r2) - cw * dt;
-      Real eb = exp_pair(zb);
-      Real es = exp_pair(zs);
+      Real eb = exp_tab(zb, tab);
+      Real es = exp_tab(zs, tab);
       if (MASK) {
         const bool act = (tile_base + c) < S.first[r];
         eb = act ? eb : Real(0);
@@ -470,6 +511,8 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ 
   constexpr int NQ = D;
   __shared__ Rec s_rec[2][kTile];
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
+  __shared__ double s_exptab[64];   // 2^(j/64) for exp_tab
+  fill_exp_table(s_exptab);
   const int rid = find_req(reqs, nreq, blockIdx.x, 0);
   const ReqDesc& rq = reqs[rid];
   if (uni(glb(rq.status)[kStData]) != 0) return;
@@ -526,9 +569,9 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ 
     if (tile_culled<D, MIX>(t_row0, &s_rec[buf][0], tile, kp)) {
       // nothing to add: the tile's column sums stay zero
     } else if (full) {
-      pass2_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+      pass2_tile<D, MIX, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp, s_exptab);
     } else {
-      pass2_tile<D, MIX, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
+      pass2_tile<D, MIX, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp, s_exptab);
     }
 
   }
