@@ -50,6 +50,9 @@ __device__ __forceinline__ float exp_pair(float z) { return __builtin_amdgcn_exp
 // in two fused steps (ln2/64 split into a double and its remainder), so r is
 // exact to ~1e-18 for every |z| < 1e4.  ldexp rounds once, also into the
 // subnormal range; arguments below -746, where exp is 0, return exactly 0.
+#ifndef HK_FP64_UNROLL
+#define HK_FP64_UNROLL 4   // column steps per loop trip in the float64 passes
+#endif
 #ifndef HK_FP64_EXP_TABLE
 #define HK_FP64_EXP_TABLE 1
 #endif
@@ -299,7 +302,7 @@ __device__ __forceinline__ void pass1_tile(Pass1Rows<D, MIX>& S, const typename 
   static_assert(!MIX, "the float32 passes use the lane-rotation kernels");
   const Real cb = Real(kp.alpha), ct = Real(kp.beta), cg = Real(kp.gamma), cw = Real(kp.omega);
   const Real sh = Real(0);
-#pragma unroll 4
+#pragma unroll HK_FP64_UNROLL
   for (int k = 0; k < 64; ++k) {
     const int c = lane ^ k;
     const auto col = cols[c];
@@ -464,7 +467,7 @@ __device__ __forceinline__ void pass2_tile(Pass2Rows<D, MIX>& S, const typename 
   static_assert(!MIX, "the float32 passes use the lane-rotation kernels");
   const Real cb = Real(kp.alpha), ct = Real(kp.beta), cg = Real(kp.gamma), cw = Real(kp.omega);
   const Real sh = Real(0);
-#pragma unroll 4
+#pragma unroll HK_FP64_UNROLL
   for (int k = 0; k < 64; ++k) {
     const int c = lane ^ k;
     const auto col = cols[c];
