@@ -121,11 +121,11 @@ def test_config2_full_size(c2_ref, prec):
     assert np.all(np.abs(gx.sum(0)) <= (1e-12 if prec == "fp64" else 1e-6) * scale)
 
 
-def _isolated_case():
+def _isolated_case(lo=-700.0, hi=-630.0):
     """Moves event 5 about 28 bandwidths away (log rate near -300 relative to
     the pair weight: below the float32 window) and event 200 just far enough
-    that its log rate falls between -700 and -630 (below the float64 path's
-    2^-900 window, yet still positive in float64)."""
+    that its log rate falls between lo and hi (by default -700 to -630: below
+    the float64 path's 2^-900 window, yet still positive in float64)."""
     w = W.random_case(31, 400, 2, t_span=10.0)
     p = np.array([0.5, 1.0, 1.0, 0.3, 1.0, 0.5])
     d = 2
@@ -133,11 +133,11 @@ def _isolated_case():
                p[3] * p[4] * (2 * np.pi) ** (-d / 2) / p[5] ** d)
     x = w.x.copy()
     x[5] += 20.0   # both coordinates: about 28 bandwidths away
-    for off in np.arange(26.0, 30.0, 0.05):
+    for off in np.arange(26.0, 34.0, 0.05):
         x[200] = w.x[200] - off
         lam, _ = oracle.rates(x, w.t, p)
         rel = np.log(lam[200] / cmax) if lam[200] > 0 else -np.inf
-        if -700 < rel < -630:
+        if lo < rel < hi:
             return x, w.t, p
     raise AssertionError("could not place the isolated event")
 
@@ -152,6 +152,29 @@ def test_isolated_events_fixup(prec):
     lam, _ = oracle.rates(x, t, p)
     say(f"case isolated prec={prec} min log lam {np.log(lam).min():.1f}")
     check(prec, *run_gpu(x, t, p, prec), ll_ref, gx_ref, gp_ref, p, len(t), label="isolated")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_isolated_event_subnormal_rate(prec):
+    """An event whose rate is a float64 subnormal (about 1e-308), so every
+    pair term it gets lies in the range where exp rounds into subnormals."""
+    x, t, p = _isolated_case(-744.0, -600.0)
+    # bisect the offset of event 200 (its rate falls as it moves away) to a
+    # rate of 1e-308: subnormal, while 1/rate still fits in float64
+    x0 = x[200] + 0.0
+    lo, hi = -3.0, 3.0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        x[200] = x0 - mid
+        lam, _ = oracle.rates(x, t, p)
+        lo, hi = (mid, hi) if lam[200] > 1e-308 else (lo, mid)
+    x[200] = x0 - lo
+    lam, _ = oracle.rates(x, t, p)
+    st, ll_ref, gx_ref, gp_ref = oracle.loglik_grad(x, t, p, threads=True)
+    assert st == 0 and np.all(np.isfinite(gp_ref)) and np.all(np.isfinite(gx_ref))
+    say(f"case subnormal rate prec={prec} min rate {lam.min():.3e}")
+    assert 1.0 / np.finfo(np.float64).max < lam.min() < np.finfo(np.float64).tiny
+    check(prec, *run_gpu(x, t, p, prec), ll_ref, gx_ref, gp_ref, p, len(t), label="subnormal rate")
 
 
 @pytest.mark.parametrize("prec", PRECS)
