@@ -175,11 +175,14 @@ def main():
         gx_all = gx.clone()
         culling = {"note": "column tiles whose pair terms all underflow are skipped; results bitwise equal"}
         for base in ([args.prec] + (["fp64"] if args.prec == "mixed" and args.fp64_steps > 0 else [])):
-            # all-pairs timed again right before the culled steps, so that both
-            # run in the same clock state
-            sec_all, _, ll_ref = run(base, args.cull_steps, 1, 0)
-            ref = gx.clone()
-            sec_c, _, ll_c = run(base + "+cull", args.cull_steps, 1, 0)
+            # all-pairs and culled steps timed in three alternating rounds, best
+            # of each, so that both see the same clock states
+            sec_all = sec_c = float("inf")
+            for _ in range(3):
+                s_a, _, ll_ref = run(base, args.cull_steps, 1, 0)
+                ref = gx.clone()
+                s_c, _, ll_c = run(base + "+cull", args.cull_steps, 1, 0)
+                sec_all, sec_c = min(sec_all, s_a), min(sec_c, s_c)
             culling[base] = {"ms_per_step": sec_c * 1e3, "all_pairs_ms_per_step": sec_all * 1e3,
                              "speedup_vs_all_pairs": sec_all / sec_c,
                              "bitwise_equal": bool(ll_c == ll_ref and torch.equal(gx, ref))}

@@ -43,46 +43,64 @@ template <int D> struct Traits<D, false> {
 __device__ __forceinline__ float exp_pair(float z) { return __builtin_amdgcn_exp2f(z); }
 
 // Float64 exp of the pair passes, by Tang's table-driven method (P. T. P. Tang,
-// ACM Trans. Math. Softw. 15(2), 1989) with 64 table entries tab[j] = 2^(j/64)
-// held in LDS: z = (64 m + j) ln2/64 + r with |r| <= ln2/128, and
-// exp(z) = 2^m tab[j] (1 + p(r)), p the degree-5 Taylor polynomial of expm1
-// (truncation below r^6/720 < 4e-17 relative).  The reduction subtracts k ln2/64
-// in two fused steps (ln2/64 split into a double and its remainder), so r is
-// exact to ~1e-18 for every |z| < 1e4.  ldexp rounds once, also into the
-// subnormal range; arguments below -746, where exp is 0, return exactly 0.
+// ACM Trans. Math. Softw. 15(2), 1989) with 2^B table entries tab[j] = 2^(j/2^B)
+// held in LDS: z = (2^B m + j) ln2/2^B + r with |r| <= ln2/2^(B+1), and
+// exp(z) = 2^m tab[j] (1 + p(r)), p the Taylor polynomial of expm1 of degree 5
+// (B = 6) or 4 (B = 8), truncated below 4e-17 relative either way.  The
+// reduction subtracts k ln2/2^B in two fused steps (ln2/2^B split into a double
+// and its remainder), so r is exact to ~1e-18.  ldexp rounds once, also into
+// the subnormal range.  Arguments are first clamped at -1100: exp is 0 below
+// -746, ldexp returns exactly 0 for such scales, and the clamp keeps k in range
+// (and maps -inf to 0).
 #ifndef HK_FP64_UNROLL
 #define HK_FP64_UNROLL 4   // column steps per loop trip in the float64 passes
 #endif
 #ifndef HK_FP64_EXP_TABLE
 #define HK_FP64_EXP_TABLE 1
 #endif
+#ifndef HK_FP64_EXP_BITS
+#define HK_FP64_EXP_BITS 8
+#endif
+constexpr int kExpTab = 1 << HK_FP64_EXP_BITS;
 __device__ __forceinline__ double exp_tab(double z, const double* __restrict__ tab) {
 #if HK_FP64_EXP_TABLE
+#if HK_FP64_EXP_BITS == 6
   constexpr double kInvStep = 92.33248261689366;        // 64 / ln2
   constexpr double kStepHi = 0x1.62e42fefa39efp-7;       // ln2 / 64, rounded
   constexpr double kStepLo = 0x1.abc9e3b39803fp-62;      // ln2 / 64 - kStepHi
+#elif HK_FP64_EXP_BITS == 8
+  constexpr double kInvStep = 369.3299304675746;        // 256 / ln2
+  constexpr double kStepHi = 0x1.62e42fefa39efp-9;       // ln2 / 256, rounded
+  constexpr double kStepLo = 0x1.abc9e3b39803fp-64;      // ln2 / 256 - kStepHi
+#else
+#error "HK_FP64_EXP_BITS must be 6 or 8"
+#endif
+  z = __builtin_fmax(z, -1100.0);
   const double kf = __builtin_rint(z * kInvStep);
   const int k = (int)kf;
   double r = __builtin_fma(-kf, kStepHi, z);
   r = __builtin_fma(-kf, kStepLo, r);
+#if HK_FP64_EXP_BITS == 6
   double p = __builtin_fma(r, 1.0 / 120.0, 1.0 / 24.0);
   p = __builtin_fma(r, p, 1.0 / 6.0);
+#else
+  double p = __builtin_fma(r, 1.0 / 24.0, 1.0 / 6.0);
+#endif
   p = __builtin_fma(r, p, 0.5);
   p = __builtin_fma(r, p, 1.0);
   p = r * p;
-  const double tj = tab[k & 63];
-  const double v = __builtin_ldexp(__builtin_fma(tj, p, tj), k >> 6);
-  return z < -746.0 ? 0.0 : v;
+  const double tj = tab[k & (kExpTab - 1)];
+  return __builtin_ldexp(__builtin_fma(tj, p, tj), k >> HK_FP64_EXP_BITS);
 #else
   (void)tab;
   return exp(z);
 #endif
 }
 
-// Fills the 64-entry table of exp_tab; the caller synchronizes the workgroup
-// before the first use.
+// Fills the table of exp_tab; the caller synchronizes the workgroup before
+// the first use.
 __device__ __forceinline__ void fill_exp_table(double* tab) {
-  if (threadIdx.x < 64) tab[threadIdx.x] = exp2((double)threadIdx.x * (1.0 / 64.0));
+  for (int j = threadIdx.x; j < kExpTab; j += blockDim.x) tab[j] = exp2((double)j / kExpTab);
 }
 
 __device__ __forceinline__ double block_max_256(double v, double* sh) {
@@ -358,7 +376,7 @@ __global__ void __launch_bounds__(kThreads) k_pass1(const ReqDesc* __restrict__ 
   constexpr int NQ = 3;
   __shared__ Rec s_rec[2][kTile];
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
-  __shared__ double s_exptab[64];   // 2^(j/64) for exp_tab
+  __shared__ double s_exptab[kExpTab];   // 2^(j/kExpTab) for exp_tab
   fill_exp_table(s_exptab);
   const int rid = find_req(reqs, nreq, blockIdx.x, 0);
   const ReqDesc& rq = reqs[rid];
@@ -514,7 +532,7 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ 
   constexpr int NQ = D;
   __shared__ Rec s_rec[2][kTile];
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
-  __shared__ double s_exptab[64];   // 2^(j/64) for exp_tab
+  __shared__ double s_exptab[kExpTab];   // 2^(j/kExpTab) for exp_tab
   fill_exp_table(s_exptab);
   const int rid = find_req(reqs, nreq, blockIdx.x, 0);
   const ReqDesc& rq = reqs[rid];
