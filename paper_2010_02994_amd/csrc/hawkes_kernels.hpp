@@ -76,8 +76,13 @@ __device__ __forceinline__ double exp_tab(double z, const double* __restrict__ t
 #error "HK_FP64_EXP_BITS must be 6 or 8"
 #endif
   z = __builtin_fmax(z, -1100.0);
-  const double kf = __builtin_rint(z * kInvStep);
-  const int k = (int)kf;
+  // k = z 2^B/ln2 rounded to an integer by adding 1.5 * 2^52 (the sum's unit
+  // in the last place is 1, so the low word of its bits is k in two's
+  // complement; exact for |k| < 2^31, and |k| < 410,000 after the clamp)
+  constexpr double kRound = 0x1.8p52;
+  const double kb = __builtin_fma(z, kInvStep, kRound);
+  const int k = __double2loint(kb);
+  const double kf = kb - kRound;
   double r = __builtin_fma(-kf, kStepHi, z);
   r = __builtin_fma(-kf, kStepLo, r);
 #if HK_FP64_EXP_BITS == 6
@@ -319,12 +324,11 @@ __device__ __forceinline__ void pass1_tile(Pass1Rows<D, MIX>& S, const typename 
   // base-2 (mixed) or natural (float64) exponent scales
   static_assert(!MIX, "the float32 passes use the lane-rotation kernels");
   const Real cb = Real(kp.alpha), ct = Real(kp.beta), cg = Real(kp.gamma), cw = Real(kp.omega);
-  const Real sh = Real(0);
 #pragma unroll HK_FP64_UNROLL
   for (int k = 0; k < 64; ++k) {
     const int c = lane ^ k;
     const auto col = cols[c];
-    Real cK = 0, cR = 0, cU = 0;
+    Real cK, cR, cU;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       Real r2 = 0;
@@ -334,32 +338,26 @@ __device__ __forceinline__ void pass1_tile(Pass1Rows<D, MIX>& S, const typename 
         r2 = dx * dx + r2;
       }
       const Real dt = S.t[r] - col.v[D];
-      const Real u = cb * r2;
-      const Real v = ct * (dt * dt);
-      const Real ys = cg * r2;
-      const Real ws = cw * dt;
-      Real eb = exp_tab((sh - u) - v, tab);
-      Real es = exp_tab((sh - ys) - ws, tab);
+      const Real dt2 = dt * dt;
+      // exponents as one product plus a fused multiply-add each
+      Real eb = exp_tab(-__builtin_fma(cb, r2, ct * dt2), tab);
+      Real es = exp_tab(-__builtin_fma(cg, r2, cw * dt), tab);
       if (MASK) {
         const bool act = (tile_base + c) < S.first[r];
         eb = act ? eb : Real(0);
         es = act ? es : Real(0);
       }
-      // the float64 path accumulates raw r2, dt^2, dt; the mixed path the
-      // dimensionless exponent parts (rescaled when the sums are reduced)
-      const Real mu_ = MIX ? u : r2;
-      const Real mv_ = MIX ? v : dt * dt;
-      const Real my_ = MIX ? ys : r2;
-      const Real mw_ = MIX ? ws : dt;
+      // raw r2, dt^2 and dt moments
       S.a[r][0] += eb;
-      S.a[r][1] = eb * mu_ + S.a[r][1];
-      S.a[r][2] = eb * mv_ + S.a[r][2];
+      S.a[r][1] = eb * r2 + S.a[r][1];
+      S.a[r][2] = eb * dt2 + S.a[r][2];
       S.a[r][3] += es;
-      S.a[r][4] = es * my_ + S.a[r][4];
-      S.a[r][5] = es * mw_ + S.a[r][5];
-      cK += eb;
-      cR = eb * mu_ + cR;
-      cU = eb * mv_ + cU;
+      S.a[r][4] = es * r2 + S.a[r][4];
+      S.a[r][5] = es * dt + S.a[r][5];
+      // column contributions summed over this lane's rows
+      cK = r == 0 ? eb : cK + eb;
+      cR = r == 0 ? eb * r2 : eb * r2 + cR;
+      cU = r == 0 ? eb * dt2 : eb * dt2 + cU;
     }
     atomicAdd(&acc_w[0 * 64 + c], cK);
     atomicAdd(&acc_w[1 * 64 + c], cR);
@@ -484,7 +482,6 @@ __device__ __forceinline__ void pass2_tile(Pass2Rows<D, MIX>& S, const typename 
   const int lane = threadIdx.x & 63;
   static_assert(!MIX, "the float32 passes use the lane-rotation kernels");
   const Real cb = Real(kp.alpha), ct = Real(kp.beta), cg = Real(kp.gamma), cw = Real(kp.omega);
-  const Real sh = Real(0);
 #pragma unroll HK_FP64_UNROLL
   for (int k = 0; k < 64; ++k) {
     const int c = lane ^ k;
@@ -502,10 +499,9 @@ __device__ __forceinline__ void pass2_tile(Pass2Rows<D, MIX>& S, const typename 
         r2 = dx[q] * dx[q] + r2;
       }
       const Real dt = S.t[r] - col.v[D];
-      const Real zb = (sh - cb * r2) - ct * (dt * dt);
-      const Real zs = (sh - cg * r2) - cw * dt;
-      Real eb = exp_tab(zb, tab);
-      Real es = exp_tab(zs, tab);
+      // exponents as one product plus a fused multiply-add each
+      Real eb = exp_tab(-__builtin_fma(cb, r2, ct * (dt * dt)), tab);
+      Real es = exp_tab(-__builtin_fma(cg, r2, cw * dt), tab);
       if (MASK) {
         const bool act = (tile_base + c) < S.first[r];
         eb = act ? eb : Real(0);
