@@ -351,3 +351,31 @@ def test_largest_size_identities(big_case, prec):
         ll64, gx64, gp64 = run_gpu(w.x, w.t, w.params, "fp64")
         assert abs(ll - ll64) <= 1e-5 * abs(ll64)
         assert np.linalg.norm(gx - gx64) <= 1e-4 * np.linalg.norm(gx64)
+
+
+def test_fp64_pair_exp_accuracy():
+    """Two events: each per-event term is one pair term (an exp times a
+    constant), so the float64 path's exp is checked directly against the
+    oracle's over exponents from 0 to about -580.  The bound allows a few
+    units in the last place for exp itself plus the rounding of the exponent
+    (|z| units of 2^-53), which both sides form in their own order."""
+    import torch
+    from paper_2010_02994_amd import api
+    p = np.array([0.5, 1.0, 1.0, 0.3, 1.0, 0.5])
+    t = np.array([0.0, 0.5])
+    worst, worst_ulp = 0.0, 0.0
+    for s in np.concatenate([[1e-9, 1e-3, 0.1], np.linspace(0.5, 17.0, 34)]):
+        x = np.array([[0.0], [s]])
+        ref = oracle.event_terms(x, t, p)
+        terms, _ = api.event_terms(torch.tensor(x, device="cuda:0"), torch.tensor(t, device="cuda:0"), p,
+                                   prec="fp64")
+        got = terms.cpu().numpy()
+        z_bg = 0.5 * s * s + 0.5 * 0.25          # alpha r^2 + beta dt^2
+        z_se = 1.0 * 0.5 + 2.0 * s * s           # omega dt + gamma r^2
+        for (row, col), z in (((0, 0), z_bg), ((1, 0), z_bg), ((1, 1), z_se)):
+            rel = abs(got[row, col] - ref[row, col]) / ref[row, col]
+            worst = max(worst, rel / (8.0 + 2.0 * z))
+            worst_ulp = max(worst_ulp, rel / 2.0 ** -53)
+            assert rel <= (8.0 + 2.0 * z) * 2.0 ** -53, (s, row, col, rel)
+        assert got[0, 1] == 0.0
+    say(f"  fp64 exp: worst error {worst:.4f} of the bound, {worst_ulp:.1f} units of 2^-53")
