@@ -106,8 +106,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the sharded design is described "
-              "in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (one evaluation would shard "
+              "over blocks of the unordered-pair triangle). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

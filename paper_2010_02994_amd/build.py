@@ -10,7 +10,7 @@ LIB = os.path.join(HERE, "libhawkes.so")
 PEAKS = os.path.join(HERE, "peaks")
 
 # Packed FP32 VALU ops are disabled on purpose: the compiler may form them from
-# scalar float code, and this build does not rely on them.
+# scalar float code, and the library does not rely on them.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
             "-packed-fp32-ops"]
 
