@@ -260,7 +260,11 @@ __global__ void __launch_bounds__(kEvBlock) k_pack(const ReqDesc* __restrict__ r
       rr.v[k] = MIX ? Real((v - glb(rq.dconst)[1 + k]) * rq.kp.inv_tx) : Real(v);
     }
     rr.v[D] = MIX ? Real((ti - glb(rq.dconst)[1 + kMaxD]) * rq.kp.inv_tt) : Real(ti);
-    int lo = 0, hi = i;   // lower_bound of ti in t[0..i]
+    // first index with time ti: i itself unless the previous event ties
+    // (then a lower_bound of ti in t[0..i], a chain of dependent loads that
+    // only tied events pay)
+    int lo = 0, hi = i;
+    if (i == 0 || t[i - 1] < ti) lo = i;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
       if (t[mid] < ti) lo = mid + 1; else hi = mid;
