@@ -173,7 +173,7 @@ __device__ __forceinline__ void init_block(const ReqDesc& rq) {
   const auto x = glb(rq.x);
   const auto t = glb(rq.t);
   const int n = rq.kp.n, nb = rq.kp.nb, L = rq.kp.L;
-  __shared__ int s_scan[1024];
+  __shared__ int s_wsum[1024 / 64];
   const int tid = threadIdx.x;
   if (tid == 0) {
     glb(rq.status)[kStData] = 0;
@@ -194,15 +194,19 @@ __device__ __forceinline__ void init_block(const ReqDesc& rq) {
       local += (nt + L - 1) / L;
     }
   }
-  s_scan[tid] = local;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int v = tid >= off ? s_scan[tid - off] : 0;
-    __syncthreads();
-    s_scan[tid] += v;
-    __syncthreads();
+  // exclusive scan of the item counts: within each wave by shuffles, then
+  // the totals of the earlier waves (one barrier instead of twenty)
+  const int lane = tid & 63, wv = tid >> 6;
+  int incl = local;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
   }
-  int base = s_scan[tid] - local;
+  if (lane == 63) s_wsum[wv] = incl;
+  __syncthreads();
+  int base = incl - local;
+  for (int w2 = 0; w2 < wv; ++w2) base += s_wsum[w2];
   for (int q = 0; q < per; ++q) {
     const int pos = tid * per + q;
     if (pos < nb) {
