@@ -317,32 +317,44 @@ __global__ void __launch_bounds__(kFinalThreads) k_bmds_final(Args a, int D) {
 }
 
 // Per event: its row partials over the chunks of its band, then its column
-// partials over the bands that reach its chunk (fixed order).
+// partials over the bands that reach its chunk.  Four lanes share an event
+// (each takes every fourth chunk and band, in order; two butterfly steps
+// combine the four sums in a fixed order, the same on every lane), so the
+// first events, whose columns collect a partial from nearly every band, do not
+// keep one long chain of loads each.
+constexpr int kRedEvents = 64;   // events per workgroup of k_bmds_reduce (256 lanes)
+
 template <int D>
-__global__ void __launch_bounds__(256) k_bmds_reduce(Args a) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= a.n) return;
+__global__ void __launch_bounds__(4 * kRedEvents) k_bmds_reduce(Args a) {
+  const int n = blockIdx.x * kRedEvents + (threadIdx.x >> 2);
+  const int sub = threadIdx.x & 3;
+  const bool live = n < a.n;
+  const bool bad = a.out4[3] != 0.0;
   double g[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) g[q] = 0.0;
-  if (a.out4[3] != 0.0) {
+  if (live && !bad) {
+    const int I = n / kTR, r = n % kTR;
+    const int64_t o = band_offset(I);
+    for (int J = sub; J <= I / 4; J += 4)
 #pragma unroll
-    for (int q = 0; q < D; ++q) a.grad_x[(int64_t)n * D + q] = NAN;
-    return;
+      for (int q = 0; q < D; ++q) g[q] += a.prow[((o + J) * kTR + r) * D + q];
+    const int J = n / kTC, c = n % kTC;
+    for (int Ib = 4 * J + sub; Ib < a.nb; Ib += 4)
+#pragma unroll
+      for (int q = 0; q < D; ++q) g[q] += a.pcol[((band_offset(Ib) + J) * kTC + c) * D + q];
   }
-  const int I = n / kTR, r = n % kTR;
-  const int64_t o = band_offset(I);
-  for (int J = 0; J <= I / 4; ++J)
+  // the four lanes of an event are adjacent lanes of one wave, all present
 #pragma unroll
-    for (int q = 0; q < D; ++q) g[q] += a.prow[((o + J) * kTR + r) * D + q];
-  const int J = n / kTC, c = n % kTC;
-  for (int Ib = 4 * J; Ib < a.nb; ++Ib)
-#pragma unroll
-    for (int q = 0; q < D; ++q) g[q] += a.pcol[((band_offset(Ib) + J) * kTC + c) * D + q];
+  for (int q = 0; q < D; ++q) {
+    g[q] += __shfl_xor(g[q], 1);
+    g[q] += __shfl_xor(g[q], 2);
+  }
+  if (!live || sub != 0) return;
 #pragma unroll
   for (int q = 0; q < D; ++q) {
     const int64_t e = (int64_t)n * D + q;
-    a.grad_x[e] = a.accumulate ? a.grad_x[e] + g[q] : g[q];
+    a.grad_x[e] = bad ? NAN : (a.accumulate ? a.grad_x[e] + g[q] : g[q]);
   }
 }
 
@@ -378,7 +390,8 @@ static void launch(const Args& a, int prec, hipStream_t s, int phase) {
     }
     k_bmds_final<<<1, kFinalThreads, 0, s>>>(a, D);
   }
-  if (phase != 1 && a.grad_x) k_bmds_reduce<D><<<(a.n + 255) / 256, 256, 0, s>>>(a);
+  if (phase != 1 && a.grad_x)
+    k_bmds_reduce<D><<<(a.n + kRedEvents - 1) / kRedEvents, 4 * kRedEvents, 0, s>>>(a);
 }
 
 }  // namespace bmds
