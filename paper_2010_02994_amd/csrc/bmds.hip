@@ -177,13 +177,18 @@ __global__ void __launch_bounds__(TileShape<C>::kLanes) k_bmds_tiles(Args a) {
     jl[c] = w * 64 * C + c * 64 + lane;
     jc[c] = J * kTC + jl[c];
   }
+  // the band's first tile also counts its rows' non-finite coordinates, so
+  // every event is checked once
+  int bad = 0;
   for (int e = threadIdx.x; e < kTR * D; e += NL) {
     const int r = e / D, q = e % D;
     const int i = i0 + r;
-    s_x[r][q] = i < a.n ? (R)a.x[(int64_t)i * D + q] : R(0);
+    const double xv = i < a.n ? a.x[(int64_t)i * D + q] : 0.0;
+    if (J == 0 && !isfinite(xv)) ++bad;
+    s_x[r][q] = (R)xv;
   }
   R xj[C][D], g[C][D], tsum[C], dsum[C];
-  int cnt = 0, bad = 0;
+  int cnt = 0;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     tsum[c] = R(0);
@@ -296,19 +301,17 @@ __global__ void __launch_bounds__(TileShape<C>::kLanes) k_bmds_tiles(Args a) {
 }
 
 // One workgroup: the tile totals in tile order, the -M/2 log sigma^2 and
-// -M/sigma terms, and the data checks (invalid deltas, non-finite x).
-__global__ void __launch_bounds__(kFinalThreads) k_bmds_final(Args a, int D) {
-  __shared__ double sh[5 * kFinalThreads];
-  double v[5] = {0, 0, 0, 0, 0};   // four tile totals, then the non-finite coordinates
+// -M/sigma terms, and the data checks (invalid deltas and non-finite x, both
+// counted by the tiles).
+__global__ void __launch_bounds__(kFinalThreads) k_bmds_final(Args a) {
+  __shared__ double sh[4 * kFinalThreads];
+  double v[4] = {0, 0, 0, 0};   // the four tile totals
   for (int64_t t = threadIdx.x; t < a.ntiles; t += kFinalThreads)
     for (int k = 0; k < 4; ++k) v[k] += a.ptile[t * 4 + k];
-  for (int64_t e = threadIdx.x; e < (int64_t)a.n * D; e += kFinalThreads)
-    if (!isfinite(a.x[e])) v[4] += 1.0;
   block_sum_n(v, sh);
-  const double nonfinite = v[4];
   if (threadIdx.x == 0) {
     const double M = v[2];
-    const bool bad = v[3] > 0.0 || nonfinite > 0.0;
+    const bool bad = v[3] > 0.0;
     a.out4[0] = bad ? NAN : -0.5 * M * log(a.sigma * a.sigma) + v[0];
     a.out4[1] = bad ? NAN : -M * a.inv_sigma + v[1];
     a.out4[2] = M;
@@ -388,7 +391,7 @@ static void launch(const Args& a, int prec, hipStream_t s, int phase) {
       if (wide) k_bmds_tiles<D, false, kColsFp64><<<nt, TileShape<kColsFp64>::kLanes, 0, s>>>(a);
       else k_bmds_tiles<D, false, 1><<<nt, TileShape<1>::kLanes, 0, s>>>(a);
     }
-    k_bmds_final<<<1, kFinalThreads, 0, s>>>(a, D);
+    k_bmds_final<<<1, kFinalThreads, 0, s>>>(a);
   }
   if (phase != 1 && a.grad_x)
     k_bmds_reduce<D><<<(a.n + kRedEvents - 1) / kRedEvents, 4 * kRedEvents, 0, s>>>(a);

@@ -53,6 +53,18 @@ def test_bmds_invalid_delta_is_reported():
     assert o[3] == -3 and np.isnan(o[0]) and np.all(np.isnan(gx))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("row", [0, 63, 64, 299])
+def test_bmds_nonfinite_coordinate_is_reported(prec, row):
+    """A non-finite coordinate in any row band (first and last rows of a
+    band, the last event) makes the call report a data error."""
+    c = W.bmds_case(7, 300, 2)
+    c.x[row, 1] = np.inf if row % 2 else np.nan
+    say(f"case bmds non-finite x row={row} prec={prec}")
+    o, gx = _gpu(c, prec)
+    assert o[3] == -3 and np.isnan(o[0]) and np.isnan(o[1]) and np.all(np.isnan(gx))
+
+
 def test_bmds_deterministic():
     c = W.bmds_case(8, 900, 3, missing=0.2)
     say("case bmds determinism")
