@@ -89,6 +89,14 @@ __device__ __forceinline__ R dpp_step(R v) {
 // t exp(-w^2 + P(t)), t = 1/(1 + w/2), of Press et al., Numerical Recipes
 // (2nd ed., Sec. 6.2, "erfcc"), relative error below 1.2e-7 for all w >= 0,
 // built on the hardware reciprocal and base-2 exponential.
+// Beyond z = 6 the upper tail q = erfc(z/sqrt2)/2 < 1e-9 (erfc_cheb's
+// relative error is below 1.2e-7), far below half a float32 unit of 1
+// (2^-25 = 3.0e-8), so 1 - q rounds to exactly 1.
+#ifndef HK_BMDS_FAR_Z
+#define HK_BMDS_FAR_Z 6.0f
+#endif
+constexpr float kFarZ = HK_BMDS_FAR_Z;
+
 __device__ __forceinline__ float erfc_cheb(float w) {
   const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, w, 1.0f));
   float p = 0.17087277f;
@@ -114,11 +122,20 @@ __device__ __forceinline__ void pair_terms(R r2, R delta, R inv_sigma, R inv_s2,
     const float dist = r2 * rs;
     const float z = dist * inv_sigma;
     const float res = delta - dist;
-    const float q = 0.5f * erfc_cheb(z * 0.70710678118654752f);
-    const float phi = 1.0f - q;
-    const float lphi = __builtin_amdgcn_logf(phi) * 0.69314718055994531f;
     const float pdf = 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.72134752044448170f * z * z);
-    const float rho = pdf * __builtin_amdgcn_rcpf(phi);
+    float lphi, rho;
+    if (__all(z > kFarZ)) {
+      // every pair of the wave lies beyond kFarZ standard deviations: there
+      // 1 - q rounds to 1 in float32, so log(phi) = 0 and pdf / phi = pdf
+      // exactly, and the erfc, log and reciprocal are skipped
+      lphi = 0.0f;
+      rho = pdf;
+    } else {
+      const float q = 0.5f * erfc_cheb(z * 0.70710678118654752f);
+      const float phi = 1.0f - q;
+      lphi = __builtin_amdgcn_logf(phi) * 0.69314718055994531f;
+      rho = pdf * __builtin_amdgcn_rcpf(phi);
+    }
     term = -0.5f * res * res * inv_s2 - lphi;
     dsig = (res * res * inv_s2 + rho * z) * inv_sigma;
     coef = (res * inv_s2 - rho * inv_sigma) * rs;
