@@ -144,9 +144,17 @@ __device__ __forceinline__ void pair_terms(R r2, R delta, R inv_sigma, R inv_s2,
     const double z = dist * inv_sigma;
     const double res = delta - dist;
     const double q = 0.5 * erfc(z * 0.70710678118654752440);
-    const double lphi = log1p(-q);
     const double pdf = 0.39894228040143267794 * exp(-0.5 * z * z);
-    const double rho = pdf / (1.0 - q);
+    double lphi, rho;
+    if (__all(z > (double)kFarZ)) {
+      // q < 1e-9 on every lane: log(1 - q) = -q (1 + q/2 + q^2/3 + ...) and
+      // 1/(1 - q) = 1 + q + q^2 + ..., both truncated below q^3 < 1e-27
+      lphi = -q * __builtin_fma(q, __builtin_fma(q, 1.0 / 3.0, 0.5), 1.0);
+      rho = pdf * __builtin_fma(q, 1.0 + q, 1.0);
+    } else {
+      lphi = log1p(-q);
+      rho = pdf / (1.0 - q);
+    }
     term = -0.5 * res * res * inv_s2 - lphi;
     dsig = (res * res * inv_s2 + rho * z) * inv_sigma;
     coef = dist > 0.0 ? (res * inv_s2 - rho * inv_sigma) / dist : 0.0;
