@@ -268,7 +268,8 @@ __global__ void __launch_bounds__(kBlock) k_mwg_exact(Step s) {
     double a = 0.0, b = 0.0;
     for (int j = j0 + threadIdx.x; j < j1; j += kBlock) {
       if (j == r) continue;
-      const int pos = find_moved(s.idx, s.nmove, j);
+      // k_mwg_rows flagged the moved rows with 2: only they search the list
+      const int pos = s.flag[j] == 2 ? find_moved(s.idx, s.nmove, j) : -1;
       double xj[D];
 #pragma unroll
       for (int q = 0; q < D; ++q) xj[q] = pos >= 0 ? s.xnew[(int64_t)pos * D + q] : s.x[(int64_t)j * D + q];
