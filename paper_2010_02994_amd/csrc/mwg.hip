@@ -65,7 +65,7 @@ struct Step {
 // times) and self-excitation per unit theta (only from strictly earlier j).
 template <int D>
 __device__ __forceinline__ void pair_ab(const Model& m, const double* xi, double ti, const double* xj, double tj,
-                                        double& a, double& b) {
+                                        double& a, double& b, const double* __restrict__ tab) {
   double r2 = 0.0;
 #pragma unroll
   for (int q = 0; q < D; ++q) {
@@ -73,8 +73,8 @@ __device__ __forceinline__ void pair_ab(const Model& m, const double* xi, double
     r2 = fma(dx, dx, r2);
   }
   const double dt = ti - tj;
-  a = dt != 0.0 ? m.cbg_unit * exp(-m.alpha * r2 - m.beta * dt * dt) : 0.0;
-  b = dt > 0.0 ? m.cse_unit * exp(-m.omega * dt - m.gamma * r2) : 0.0;
+  a = dt != 0.0 ? m.cbg_unit * exp_tab(-m.alpha * r2 - m.beta * dt * dt, tab) : 0.0;
+  b = dt > 0.0 ? m.cse_unit * exp_tab(-m.omega * dt - m.gamma * r2, tab) : 0.0;
 }
 
 // Position of event j in the moved list, or -1 (binary search; the list is
@@ -118,6 +118,8 @@ __global__ void __launch_bounds__(kBlock) k_mwg_rows(Step s) {
   __shared__ int s_j[kBlock];
   __shared__ double sh[kBlock];
   __shared__ int s_wcnt[kBlock / 64];
+  __shared__ double s_exptab[kExpTab];   // 2^(j/kExpTab) for exp_tab (read after the loop's barrier)
+  fill_exp_table(s_exptab);
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const bool row = i < s.n;
   double xi[D], ti = 0.0;
@@ -150,8 +152,8 @@ __global__ void __launch_bounds__(kBlock) k_mwg_rows(Step s) {
           continue;
         }
         double a0, b0, a1, b1;
-        pair_ab<D>(s.m, xi, ti, s_old[k], s_t[k], a0, b0);
-        pair_ab<D>(s.m, xi, ti, s_new[k], s_t[k], a1, b1);
+        pair_ab<D>(s.m, xi, ti, s_old[k], s_t[k], a0, b0, s_exptab);
+        pair_ab<D>(s.m, xi, ti, s_new[k], s_t[k], a1, b1, s_exptab);
         da += a1 - a0;
         db += b1 - b0;
         oa += a0;
@@ -222,6 +224,8 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_mwg_exact(Step s) {
   __shared__ double sh[2 * kBlock];
   __shared__ int s_scan[kBlock];
+  __shared__ double s_exptab[kExpTab];   // 2^(j/kExpTab) for exp_tab (read after the scan's barriers)
+  fill_exp_table(s_exptab);
   const int tid = threadIdx.x;
   const int per = (s.nrb + kBlock - 1) / kBlock;
   const int lo = min(s.nrb, tid * per), hi = min(s.nrb, lo + per);
@@ -274,7 +278,7 @@ __global__ void __launch_bounds__(kBlock) k_mwg_exact(Step s) {
 #pragma unroll
       for (int q = 0; q < D; ++q) xj[q] = pos >= 0 ? s.xnew[(int64_t)pos * D + q] : s.x[(int64_t)j * D + q];
       double pa, pb;
-      pair_ab<D>(s.m, xr, tr, xj, s.t[j], pa, pb);
+      pair_ab<D>(s.m, xr, tr, xj, s.t[j], pa, pb, s_exptab);
       a += pa;
       b += pb;
     }
