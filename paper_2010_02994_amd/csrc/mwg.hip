@@ -109,46 +109,56 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // below 2^-16 of the terms it was formed from, so its rounding error could
 // exceed ~2^-37 of it) the row is listed for an exact recompute instead, so
 // float64 cancellation neither decides a move nor corrupts the cached parts.
-// Moved rows are listed too.
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_mwg_rows(Step s) {
+// Moved rows are listed too.  A workgroup covers kBlock rows with RL adjacent
+// lanes per row: each lane takes every RL-th moved event, and butterfly steps
+// combine the RL sums in a fixed order (the same on every lane), so a block of
+// many moved events is not one long chain per row.  Few moved events take one
+// lane per row (smaller workgroups start and finish sooner).
+constexpr int kRowLanesMany = 4;
+constexpr int kManyMoved = 8;   // moved events from which four lanes per row pay
+
+template <int D, int RL>
+__global__ void __launch_bounds__(RL * kBlock) k_mwg_rows(Step s) {
   __shared__ double s_old[kBlock][D];
   __shared__ double s_new[kBlock][D];
   __shared__ double s_t[kBlock];
   __shared__ int s_j[kBlock];
-  __shared__ double sh[kBlock];
-  __shared__ int s_wcnt[kBlock / 64];
+  __shared__ double s_dl[kBlock];
+  __shared__ double sh[RL * kBlock];
+  __shared__ int s_wcnt[(RL * kBlock) / 64];
   __shared__ double s_exptab[kExpTab];   // 2^(j/kExpTab) for exp_tab (read after the loop's barrier)
   fill_exp_table(s_exptab);
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int tid = threadIdx.x;
+  const int rl = tid / RL, sub = tid % RL;
+  const int i = blockIdx.x * kBlock + rl;
   const bool row = i < s.n;
   double xi[D], ti = 0.0;
 #pragma unroll
   for (int q = 0; q < D; ++q) xi[q] = row ? s.x[(int64_t)i * D + q] : 0.0;
   if (row) ti = s.t[i];
   double da = 0.0, db = 0.0, oa = 0.0, ob = 0.0;
-  bool moved = false;
+  int moved = 0;
   for (int c0 = 0; c0 < s.nmove; c0 += kBlock) {
     const int cn = min(kBlock, s.nmove - c0);
     __syncthreads();
-    if ((int)threadIdx.x < cn) {
-      const int64_t j = s.idx[c0 + threadIdx.x];
+    if (tid < cn) {
+      const int64_t j = s.idx[c0 + tid];
       const bool ok = j >= 0 && j < s.n;
-      s_j[threadIdx.x] = ok ? (int)j : -1;
+      s_j[tid] = ok ? (int)j : -1;
 #pragma unroll
       for (int q = 0; q < D; ++q) {
-        s_old[threadIdx.x][q] = ok ? s.x[j * D + q] : 0.0;
-        s_new[threadIdx.x][q] = s.xnew[(int64_t)(c0 + threadIdx.x) * D + q];
+        s_old[tid][q] = ok ? s.x[j * D + q] : 0.0;
+        s_new[tid][q] = s.xnew[(int64_t)(c0 + tid) * D + q];
       }
-      s_t[threadIdx.x] = ok ? s.t[j] : 0.0;
+      s_t[tid] = ok ? s.t[j] : 0.0;
     }
     __syncthreads();
     if (row) {
-      for (int k = 0; k < cn; ++k) {
+      for (int k = sub; k < cn; k += RL) {
         const int j = s_j[k];
         if (j < 0) continue;
         if (j == i) {
-          moved = true;
+          moved = 1;
           continue;
         }
         double a0, b0, a1, b1;
@@ -160,6 +170,15 @@ __global__ void __launch_bounds__(kBlock) k_mwg_rows(Step s) {
         ob += b0;
       }
     }
+  }
+  // the lanes of a row are adjacent lanes of one wave, all present
+#pragma unroll
+  for (int o = 1; o < RL; o <<= 1) {
+    da += __shfl_xor(da, o);
+    db += __shfl_xor(db, o);
+    oa += __shfl_xor(oa, o);
+    ob += __shfl_xor(ob, o);
+    moved |= __shfl_xor(moved, o);
   }
   int fl = 0;
   double dl = 0.0;
@@ -176,28 +195,37 @@ __global__ void __launch_bounds__(kBlock) k_mwg_rows(Step s) {
       const bool kept = lam1 > kGuard * formed_from && !(fa > 0.0 && !(na > kGuard * fa)) &&
                         !(fb > 0.0 && !(nb > kGuard * fb));
       fl = kept ? 0 : 1;
-      s.new_a[i] = na;
-      s.new_b[i] = nb;
+      if (sub == 0) {
+        s.new_a[i] = na;
+        s.new_b[i] = nb;
+      }
       if (fl == 0) dl = log1p((s.m.mu0 * da + s.m.theta * db) / lam);
     }
-    s.flag[i] = fl;
-    // listed rows: their old log-rate, for the exact change formed later
-    s.dlog[i] = fl == 0 ? dl : s.terms[(int64_t)i * 4 + 2];
+    if (sub == 0) {
+      s.flag[i] = fl;
+      // listed rows: their old log-rate, for the exact change formed later
+      s.dlog[i] = fl == 0 ? dl : s.terms[(int64_t)i * 4 + 2];
+    }
   }
-  const double bs = block_sum(dl, sh);
-  // stage the rows needing an exact recompute, in index order
-  const bool listed = row && fl != 0;
-  const unsigned long long m = __ballot(listed);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) s_wcnt[w] = __popcll(m);
+  // block sum of the rows' log-rate changes over the row order (the first
+  // kBlock threads hold the rows, the rest zeros, so the tree is the one of a
+  // kBlock-thread sum)
+  if (sub == 0) s_dl[rl] = dl;
+  __syncthreads();
+  const double bs = block_sum(tid < kBlock ? s_dl[tid] : 0.0, sh);
+  // stage the rows needing an exact recompute, in index order (one lane per row votes)
+  const bool listed = row && sub == 0 && fl != 0;
+  const unsigned long long msk = __ballot(listed);
+  const int lane = tid & 63, w = tid >> 6;
+  if (lane == 0) s_wcnt[w] = __popcll(msk);
   __syncthreads();
   int before = 0, total = 0;
-  for (int ww = 0; ww < kBlock / 64; ++ww) {
+  for (int ww = 0; ww < (RL * kBlock) / 64; ++ww) {
     if (ww < w) before += s_wcnt[ww];
     total += s_wcnt[ww];
   }
-  if (listed) s.stage[(int64_t)blockIdx.x * kBlock + before + __popcll(m & ((1ull << lane) - 1ull))] = i;
-  if (threadIdx.x == 0) {
+  if (listed) s.stage[(int64_t)blockIdx.x * kBlock + before + __popcll(msk & ((1ull << lane) - 1ull))] = i;
+  if (tid == 0) {
     s.bcount[blockIdx.x] = total;
     s.bpart[blockIdx.x] = bs;
   }
@@ -445,7 +473,10 @@ static Pieces pieces(int64_t n) {
 
 template <int D>
 static void launch(const Step& s, hipStream_t st) {
-  k_mwg_rows<D><<<s.nrb, kBlock, 0, st>>>(s);
+  if (s.nmove >= kManyMoved)
+    k_mwg_rows<D, kRowLanesMany><<<s.nrb, kRowLanesMany * kBlock, 0, st>>>(s);
+  else
+    k_mwg_rows<D, 1><<<s.nrb, kBlock, 0, st>>>(s);
   k_mwg_exact<D><<<kExactGrid, kBlock, 0, st>>>(s);
   k_mwg_settle<D><<<s.nrb, kBlock, 0, st>>>(s);
 }
