@@ -252,6 +252,7 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_mwg_exact(Step s) {
   __shared__ double sh[2 * kBlock];
   __shared__ int s_scan[kBlock];
+  __shared__ int s_wtot[kBlock / 64];
   __shared__ double s_exptab[kExpTab];   // 2^(j/kExpTab) for exp_tab (read after the scan's barriers)
   fill_exp_table(s_exptab);
   const int tid = threadIdx.x;
@@ -259,12 +260,20 @@ __global__ void __launch_bounds__(kBlock) k_mwg_exact(Step s) {
   const int lo = min(s.nrb, tid * per), hi = min(s.nrb, lo + per);
   int own = 0;
   for (int b = lo; b < hi; ++b) own += s.bcount[b];
-  s_scan[tid] = own;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const int v = tid >= off ? s_scan[tid - off] : 0;
+  // inclusive scan of the counts: within each wave by shuffles, then the
+  // totals of the earlier waves (two barriers instead of sixteen)
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+    int incl = own;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off);
+      if (lane >= off) incl += v;
+    }
+    if (lane == 63) s_wtot[wv] = incl;
     __syncthreads();
-    s_scan[tid] += v;
+    for (int w2 = 0; w2 < wv; ++w2) incl += s_wtot[w2];
+    s_scan[tid] = incl;
     __syncthreads();
   }
   const int cnt = s_scan[kBlock - 1];
