@@ -91,15 +91,18 @@ __device__ __forceinline__ int find_moved(const int64_t* idx, int nmove, int j) 
   return -1;
 }
 
+// Sum over the workgroup in a fixed order: a butterfly within each wave (every
+// lane ends with its wave's total; each step adds the same two values on both
+// lanes of a pair), then the wave totals in wave order.  Every thread calls it
+// and gets the same value; its barriers also order earlier LDS writes.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+  __syncthreads();   // sh may be written again right after
   return r;
 }
 
