@@ -45,10 +45,12 @@ def _lib(threads: bool):
         lib.oracle_loglik_grad.argtypes = [d, d, i64, ctypes.c_int, d, d, d, d]
         lib.oracle_rates.argtypes = [d, d, i64, ctypes.c_int, d, d, d]
         lib.oracle_grad_rows.argtypes = [d, d, i64, ctypes.c_int, d, d, ctypes.POINTER(i64), i64, d]
-        lib.oracle_diagnostics.argtypes = [d, d, i64, ctypes.c_int, d, ctypes.c_double, d, ctypes.POINTER(i64)]
+        lib.oracle_grad_rows_scaled.argtypes = [d, d, i64, ctypes.c_int, d, d, ctypes.POINTER(i64), i64, d, d]
+        lib.oracle_log_rates.argtypes = [d, d, i64, ctypes.c_int, d, d, d]
+        lib.oracle_param_terms.argtypes = [d, d, i64, ctypes.c_int, d, d, d]
         lib.oracle_bmds.argtypes = [d, d, i64, ctypes.c_int, ctypes.c_double, d, d]
-        for f in (lib.oracle_loglik_grad, lib.oracle_rates, lib.oracle_grad_rows, lib.oracle_diagnostics,
-                  lib.oracle_bmds):
+        for f in (lib.oracle_loglik_grad, lib.oracle_rates, lib.oracle_grad_rows, lib.oracle_grad_rows_scaled,
+                  lib.oracle_log_rates, lib.oracle_param_terms, lib.oracle_bmds):
             f.restype = ctypes.c_int
         _libs[key] = lib
     return _libs[key]
@@ -91,30 +93,65 @@ def rates(x, t, params, threads: bool = False):
     return lam, s6
 
 
-def grad_rows(x, t, params, lam, rows, threads: bool = True):
+def grad_rows(x, t, params, lam, rows, threads: bool = True, with_scale: bool = False):
+    """Location-gradient rows (App. A) of the listed events, given every rate.
+    with_scale: also each row's sum of the magnitudes of its pair
+    contributions, sum_n' |c_nn'| |x_n' - x_n| (the scale of its rounding)."""
     x, t, p = _prep(x, t, params)
     n, d = x.shape
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     lam = np.ascontiguousarray(lam, dtype=np.float64)
     out = np.zeros((rows.shape[0], d))
-    st = _lib(threads).oracle_grad_rows(_p(x), _p(t), n, d, _p(p), _p(lam),
-                                        rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                        rows.shape[0], _p(out))
+    sc = np.zeros(rows.shape[0]) if with_scale else None
+    st = _lib(threads).oracle_grad_rows_scaled(_p(x), _p(t), n, d, _p(p), _p(lam),
+                                               rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                               rows.shape[0], _p(out), _p(sc))
     if st != 0:
         raise ValueError(f"oracle_grad_rows status {st}")
-    return out
+    return (out, sc) if with_scale else out
 
 
-def diagnostics(x, t, params, log_floor=float(np.log(np.finfo(np.float32).tiny)), threads: bool = True):
+def log_rates(x, t, params, threads: bool = True):
+    """(log lambda (N,), largest log pair term of each row (N,)), in the log
+    domain, so exact also where lambda underflows double precision."""
     x, t, p = _prep(x, t, params)
     n, d = x.shape
-    mn = np.zeros(1)
-    cnt = np.zeros(1, dtype=np.int64)
-    st = _lib(threads).oracle_diagnostics(_p(x), _p(t), n, d, _p(p), ctypes.c_double(log_floor), _p(mn),
-                                          cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    ll = np.zeros(n)
+    mx = np.zeros(n)
+    st = _lib(threads).oracle_log_rates(_p(x), _p(t), n, d, _p(p), _p(ll), _p(mx))
     if st != 0:
-        raise ValueError(f"oracle_diagnostics status {st}")
-    return float(mn[0]), int(cnt[0])
+        raise ValueError(f"oracle_log_rates status {st}")
+    return ll, mx
+
+
+def param_terms(x, t, params, threads: bool = True):
+    """(sum_n v_k(n), sum_n |v_k(n)|) for the six parameter-gradient summands:
+    the gradient and the cancellation scale of each component."""
+    x, t, p = _prep(x, t, params)
+    n, d = x.shape
+    s = np.zeros(6)
+    a = np.zeros(6)
+    st = _lib(threads).oracle_param_terms(_p(x), _p(t), n, d, _p(p), _p(s), _p(a))
+    if st != 0:
+        raise ValueError(f"oracle_param_terms status {st}")
+    return s, a
+
+
+FLT_MIN_LOG = float(np.log(np.finfo(np.float32).tiny))
+
+
+def diagnostics(x, t, params, threads: bool = True, log_floor: float = FLT_MIN_LOG):
+    """The per-workload diagnostics: smallest log lambda_n, number of rows whose
+    every weighted pair term lies below exp(log_floor) (by default the smallest
+    normal single-precision number, so these rows have no term a plain float32
+    evaluation could represent), the log-likelihood, the Frobenius norm of the
+    location gradient and the parameter gradient."""
+    lg, mx = log_rates(x, t, params, threads=threads)
+    st, ll, gx, gp = loglik_grad(x, t, params, threads=threads)
+    return {"min_log_lambda": float(lg.min()), "rows_all_terms_below_floor": int((mx < log_floor).sum()),
+            "log_floor": log_floor, "status": int(st), "loglik": ll,
+            "grad_x_norm": float(np.linalg.norm(gx)) if gx is not None else None,
+            "grad_params": [float(v) for v in gp]}
 
 
 # ---------------------------------------------------------------------------

@@ -22,7 +22,7 @@
  *
  * Parameter gradient: not printed in the paper; obtained by differentiating
  * the pair terms and the compensator above term by term (the formulas are in
- * the comments of oracle_finalize below).
+ * the comment of event_param_terms below).
  *
  * Readings where the paper is silent (each listed in the design notes):
  *  - t_N is the largest event time; the time integral runs over [0, t_N].
@@ -136,9 +136,12 @@ int oracle_rates(const double* x, const double* t, int64_t n, int d, const doubl
 
 /* Location gradient rows (App. A) for the events listed in rows[], given the
  * rates lam[] of all events.  A partner whose three pair terms are exactly
- * zero adds exactly zero, so its rate is not needed beyond being finite. */
-int oracle_grad_rows(const double* x, const double* t, int64_t n, int d, const double* theta6,
-                     const double* lam, const int64_t* rows, int64_t nrows, double* out) {
+ * zero adds exactly zero, so its rate is not needed beyond being finite.
+ * scale (nrows, or NULL) receives each row's sum of the magnitudes of its
+ * pair contributions, sum_{n'} |c_{nn'}| |x_{n'} - x_n|: the size against
+ * which the rounding of any evaluation of that row is measured. */
+int oracle_grad_rows_scaled(const double* x, const double* t, int64_t n, int d, const double* theta6,
+                            const double* lam, const int64_t* rows, int64_t nrows, double* out, double* scale) {
   model m;
   if (n < 1 || d < 1 || d > 64 || !x || !t || !lam || !rows || !out) return ORACLE_EINVAL;
   if (make_model(theta6, d, &m) != ORACLE_OK) return ORACLE_EINVAL;
@@ -147,8 +150,9 @@ int oracle_grad_rows(const double* x, const double* t, int64_t n, int d, const d
 #pragma omp parallel for schedule(dynamic, 4)
   for (r = 0; r < nrows; ++r) {
     const int64_t i = rows[r];
-    ksum g[64];
+    ksum g[64], sc;
     memset(g, 0, sizeof(ksum) * d);
+    memset(&sc, 0, sizeof(sc));
     for (int64_t j = 0; j < n; ++j) {
       if (j == i) continue;
       double bg_ij, se_ij, se_ji, r2, dt, dummy_bg, dummy_r2, dummy_dt;
@@ -160,10 +164,17 @@ int oracle_grad_rows(const double* x, const double* t, int64_t n, int d, const d
       if (mu_ij == 0.0 && xi_ij == 0.0 && xi_ji == 0.0) continue;
       const double coef = (mu_ij / lam[i] + mu_ij / lam[j]) * itx2 + (xi_ij / lam[i] + xi_ji / lam[j]) * ih2;
       for (int k = 0; k < d; ++k) ks_add(&g[k], coef * (x[j * d + k] - x[i * d + k]));
+      if (scale) ks_add(&sc, fabs(coef) * sqrt(r2));
     }
     for (int k = 0; k < d; ++k) out[r * d + k] = ks_val(&g[k]);
+    if (scale) scale[r] = ks_val(&sc);
   }
   return ORACLE_OK;
+}
+
+int oracle_grad_rows(const double* x, const double* t, int64_t n, int d, const double* theta6,
+                     const double* lam, const int64_t* rows, int64_t nrows, double* out) {
+  return oracle_grad_rows_scaled(x, t, n, d, theta6, lam, rows, nrows, out, NULL);
 }
 
 /* Compensator terms per event: Lambda_n, and the pieces the parameter
@@ -178,6 +189,32 @@ static void compensator(const model* m, double T, double tn, double* Lam, double
   *dtau = -m->mu0 / (m->tau_t * m->tau_t) * ((T - tn) * std_normal_pdf(a) + tn * std_normal_pdf(-b));
   /* d/d omega of theta [1 - exp(-omega (T - t_n))] */
   *domega = m->theta * (T - tn) * exp(-m->omega * (T - tn));
+}
+
+/* Event n's share of each parameter derivative of ell (the summands of the
+ * parameter gradient), from its six unweighted row sums s = (K, R, U, J, V, W)
+ * and its rate lam; Lam receives its compensator term Lambda_n.  In the
+ * notation M = mu0 K, A = mu0 R, B = mu0 U, S = theta J, P = theta V, Q = theta W:
+ *   d/d mu0   : M_n/(mu0 lambda_n) - [Phi(a_n) - Phi(b_n)]
+ *   d/d tau_x : (A_n/tau_x^3 - D M_n/tau_x)/lambda_n
+ *   d/d tau_t : (B_n/tau_t^3 - M_n/tau_t)/lambda_n - d Lambda_n/d tau_t
+ *   d/d theta : S_n/(theta lambda_n) - [1 - exp(-omega (T - t_n))]
+ *   d/d omega : (S_n/omega - Q_n)/lambda_n - theta (T - t_n) exp(-omega (T - t_n))
+ *   d/d h     : (P_n/h^3 - D S_n/h)/lambda_n
+ * (a_n = (T - t_n)/tau_t, b_n = -t_n/tau_t), obtained by differentiating the
+ * pair terms and the compensator of Sec. 2.1 term by term. */
+static void event_param_terms(const model* m, double T, double tn, const double* s, double lam, double* Lam,
+                              double* v6) {
+  double cdf_diff, omd, dtau, domega;
+  compensator(m, T, tn, Lam, &cdf_diff, &omd, &dtau, &domega);
+  const double il = 1.0 / lam;
+  const int d = m->d;
+  v6[0] = s[0] * il - cdf_diff;
+  v6[1] = m->mu0 * (s[1] / (m->tau_x * m->tau_x * m->tau_x) - d * s[0] / m->tau_x) * il;
+  v6[2] = m->mu0 * (s[2] / (m->tau_t * m->tau_t * m->tau_t) - s[0] / m->tau_t) * il - dtau;
+  v6[3] = s[3] * il - omd;
+  v6[4] = m->theta * (s[3] / m->omega - s[5]) * il - domega;
+  v6[5] = m->theta * (s[4] / (m->h * m->h * m->h) - d * s[3] / m->h) * il;
 }
 
 /* Log-likelihood, location gradient and parameter gradient.
@@ -205,25 +242,11 @@ int oracle_loglik_grad(const double* x, const double* t, int64_t n, int d, const
   ksum sl, sL, gk[6];
   memset(&sl, 0, sizeof(sl)); memset(&sL, 0, sizeof(sL)); memset(gk, 0, sizeof(gk));
   for (int64_t i = 0; i < n; ++i) {
-    double Lam, cdf_diff, omd, dtau, domega;
-    compensator(&m, T, t[i], &Lam, &cdf_diff, &omd, &dtau, &domega);
+    double Lam, v6[6];
+    event_param_terms(&m, T, t[i], s6 + 6 * i, lam[i], &Lam, v6);
     ks_add(&sl, log(lam[i]));
     ks_add(&sL, Lam);
-    const double* s = s6 + 6 * i;
-    const double il = 1.0 / lam[i];
-    const double M_over_mu0 = s[0], S_over_theta = s[3];
-    /* d ell/d mu0    = sum M_n/(mu0 lambda_n) - sum [Phi(a_n) - Phi(b_n)] */
-    ks_add(&gk[0], M_over_mu0 * il - cdf_diff);
-    /* d ell/d tau_x  = sum (A_n/tau_x^3 - D M_n/tau_x)/lambda_n */
-    ks_add(&gk[1], m.mu0 * (s[1] / (m.tau_x * m.tau_x * m.tau_x) - d * s[0] / m.tau_x) * il);
-    /* d ell/d tau_t  = sum (B_n/tau_t^3 - M_n/tau_t)/lambda_n - sum dLambda_n/dtau_t */
-    ks_add(&gk[2], m.mu0 * (s[2] / (m.tau_t * m.tau_t * m.tau_t) - s[0] / m.tau_t) * il - dtau);
-    /* d ell/d theta  = sum S_n/(theta lambda_n) - sum [1 - exp(-omega (T - t_n))] */
-    ks_add(&gk[3], S_over_theta * il - omd);
-    /* d ell/d omega  = sum (S_n/omega - Q_n)/lambda_n - theta sum (T - t_n) exp(-omega (T - t_n)) */
-    ks_add(&gk[4], m.theta * (s[3] / m.omega - s[5]) * il - domega);
-    /* d ell/d h      = sum (P_n/h^3 - D S_n/h)/lambda_n */
-    ks_add(&gk[5], m.theta * (s[4] / (m.h * m.h * m.h) - d * s[3] / m.h) * il);
+    for (int k = 0; k < 6; ++k) ks_add(&gk[k], v6[k]);
   }
   *ll = zero ? -INFINITY : ks_val(&sl) - ks_val(&sL);
   if (grad_theta) for (int k = 0; k < 6; ++k) grad_theta[k] = zero ? NAN : ks_val(&gk[k]);
@@ -243,38 +266,87 @@ int oracle_loglik_grad(const double* x, const double* t, int64_t n, int d, const
   return zero ? ORACLE_ZERORATE : ORACLE_OK;
 }
 
-/* Diagnostics: the smallest log lambda_n and the number of rows whose every
- * weighted pair term mu_{nn'}, xi_{nn'} lies below exp(log_floor) (with
- * log_floor = log(FLT_MIN) this counts rows whose terms would all underflow
- * single precision). */
-int oracle_diagnostics(const double* x, const double* t, int64_t n, int d, const double* theta6,
-                       double log_floor, double* min_log_lam, int64_t* rows_below) {
+/* log lambda_n for every event in the log domain, exact also where lambda_n
+ * underflows double precision: each weighted pair term of Sec. 2.1 is kept as
+ * its natural logarithm,
+ *   log mu_{nn'} = log(mu0 (2 pi)^{-(D+1)/2} tau_x^{-D} tau_t^{-1}) - r^2/(2 tau_x^2) - dt^2/(2 tau_t^2)   (dt != 0)
+ *   log xi_{nn'} = log(theta omega (2 pi)^{-D/2} h^{-D}) - omega dt - r^2/(2 h^2)                          (dt > 0)
+ * and the row is summed relative to its largest term m_n:
+ *   log lambda_n = m_n + log sum exp(log term - m_n).
+ * max_log_term (or NULL) receives m_n; a row with no active pair gets -inf
+ * for both.  A zero weight (mu0 = 0 or theta = 0) contributes no terms. */
+int oracle_log_rates(const double* x, const double* t, int64_t n, int d, const double* theta6, double* log_lam,
+                     double* max_log_term) {
   model m;
-  if (n < 1 || !min_log_lam || !rows_below) return ORACLE_EINVAL;
+  if (n < 1 || d < 1 || !x || !t || !log_lam) return ORACLE_EINVAL;
   if (make_model(theta6, d, &m) != ORACLE_OK) return ORACLE_EINVAL;
-  double mn = INFINITY;
-  int64_t cnt = 0;
+  const double lbg = m.mu0 > 0 ? log(m.mu0 * m.cbg_unit) : -INFINITY;
+  const double lse = m.theta > 0 ? log(m.theta * m.cse_unit) : -INFINITY;
   int64_t i;
-#pragma omp parallel for schedule(dynamic, 16) reduction(min : mn) reduction(+ : cnt)
+#pragma omp parallel for schedule(dynamic, 16)
   for (i = 0; i < n; ++i) {
-    double s6[6];
-    row_sums(&m, x, t, n, i, s6);
-    const double l = log(row_rate(&m, s6));
-    if (l < mn) mn = l;
-    double best = -INFINITY;
+    /* first sweep: the largest log term of the row */
+    double mx = -INFINITY;
     for (int64_t j = 0; j < n; ++j) {
       if (j == i) continue;
-      double bg, se, r2, dt;
-      pair_terms(&m, x + i * d, x + j * d, t[i], t[j], &bg, &se, &r2, &dt);
-      const double lb = log(m.mu0 * bg), lsx = log(m.theta * se);
-      if (lb > best) best = lb;
-      if (lsx > best) best = lsx;
+      double r2 = 0.0;
+      for (int k = 0; k < d; ++k) { const double dx = x[i * d + k] - x[j * d + k]; r2 += dx * dx; }
+      const double dt = t[i] - t[j];
+      if (dt != 0.0) {
+        const double e = lbg - r2 / (2.0 * m.tau_x * m.tau_x) - dt * dt / (2.0 * m.tau_t * m.tau_t);
+        if (e > mx) mx = e;
+      }
+      if (dt > 0.0) {
+        const double e = lse - m.omega * dt - r2 / (2.0 * m.h * m.h);
+        if (e > mx) mx = e;
+      }
     }
-    if (best < log_floor) cnt += 1;
+    if (max_log_term) max_log_term[i] = mx;
+    if (mx == -INFINITY) { log_lam[i] = -INFINITY; continue; }
+    /* second sweep: the terms relative to the largest one */
+    ksum acc;
+    memset(&acc, 0, sizeof(acc));
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double r2 = 0.0;
+      for (int k = 0; k < d; ++k) { const double dx = x[i * d + k] - x[j * d + k]; r2 += dx * dx; }
+      const double dt = t[i] - t[j];
+      if (dt != 0.0 && lbg > -INFINITY)
+        ks_add(&acc, exp(lbg - r2 / (2.0 * m.tau_x * m.tau_x) - dt * dt / (2.0 * m.tau_t * m.tau_t) - mx));
+      if (dt > 0.0 && lse > -INFINITY) ks_add(&acc, exp(lse - m.omega * dt - r2 / (2.0 * m.h * m.h) - mx));
+    }
+    log_lam[i] = mx + log(ks_val(&acc));
   }
-  *min_log_lam = mn;
-  *rows_below = cnt;
   return ORACLE_OK;
+}
+
+/* The parameter gradient's summands over events (see event_param_terms):
+ * sum6 receives sum_n v_k(n), the parameter gradient itself, and abs6 the
+ * cancellation scale sum_n |v_k(n)| against which the rounding of any
+ * evaluation of d ell/d Theta_k is measured.  Needs every lambda_n > 0. */
+int oracle_param_terms(const double* x, const double* t, int64_t n, int d, const double* theta6, double* sum6,
+                       double* abs6) {
+  model m;
+  if (n < 1 || d < 1 || !x || !t || !sum6 || !abs6) return ORACLE_EINVAL;
+  if (make_model(theta6, d, &m) != ORACLE_OK) return ORACLE_EINVAL;
+  double* lam = (double*)malloc(sizeof(double) * n);
+  double* s6 = (double*)malloc(sizeof(double) * 6 * n);
+  if (!lam || !s6) { free(lam); free(s6); return ORACLE_EINVAL; }
+  oracle_rates(x, t, n, d, theta6, lam, s6);
+  double T = t[0];
+  for (int64_t i = 1; i < n; ++i) if (t[i] > T) T = t[i];
+  int zero = 0;
+  ksum sg[6], sa[6];
+  memset(sg, 0, sizeof(sg)); memset(sa, 0, sizeof(sa));
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(lam[i] > 0.0)) { zero = 1; break; }
+    double Lam, v6[6];
+    event_param_terms(&m, T, t[i], s6 + 6 * i, lam[i], &Lam, v6);
+    for (int k = 0; k < 6; ++k) { ks_add(&sg[k], v6[k]); ks_add(&sa[k], fabs(v6[k])); }
+  }
+  for (int k = 0; k < 6; ++k) { sum6[k] = zero ? NAN : ks_val(&sg[k]); abs6[k] = zero ? NAN : ks_val(&sa[k]); }
+  free(lam); free(s6);
+  return zero ? ORACLE_ZERORATE : ORACLE_OK;
 }
 
 /* ------------------------------------------------------------------------

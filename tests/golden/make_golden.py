@@ -1,5 +1,8 @@
-"""Writes tests/golden/oracle_small.json: inputs and oracle outputs for a few
-small seeded cases (including ties and one D=6 case).  Calls only oracle/.
+"""Writes tests/golden/oracle_small.json (inputs and oracle outputs for a few
+small seeded cases, including ties and one D=6 case) and
+tests/golden/diagnostics.json (the oracle's per-workload diagnostics for the
+four seeded benchmark workloads).  Calls only oracle/ and the seeded input
+generators.
 
 The paper prints no worked numeric example of the likelihood, so these values
 are a regression record of the pinned oracle, not published numbers."""
@@ -29,6 +32,18 @@ def cases():
     return out
 
 
+def workload_diagnostics():
+    from paper_2010_02994_amd import workloads as W
+    out = {}
+    for name, w in (("c0", W.config0()), ("c1", W.config1(snapshots=0)), ("c2", W.config2()), ("c3", W.config3())):
+        d = oracle.diagnostics(w.x, w.t, w.params)
+        d["workload"] = w.name
+        out[name] = d
+    with open(os.path.join(HERE, "diagnostics.json"), "w") as f:
+        json.dump({"source": "oracle/oracle.c (oracle_log_rates, oracle_loglik_grad) via tests/golden/make_golden.py",
+                   "workloads": out}, f, indent=1)
+
+
 def main():
     recs = []
     for x, t, p in cases():
@@ -42,3 +57,4 @@ def main():
 
 if __name__ == "__main__":
     main()
+    workload_diagnostics()
