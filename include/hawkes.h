@@ -120,6 +120,27 @@ int hawkes_grad_timed(const double* x, const double* t, int64_t n, int d, const 
                       double* loglik /* host or NULL */, double* grad_x /* device */,
                       double* grad_params /* host or NULL */, float* stage_ms /* host, 9 */);
 
+/* Diagnostics of the last evaluation enqueued with workspace ws for (n, d,
+ * prec, p) (hawkes_loglik, hawkes_grad, hawkes_grad_async, hawkes_grad_timed
+ * or hawkes_event_terms): which rows the float64 fix-up recomputed.  The pair
+ * passes take each rate lambda_n (Sec. 2.1) from sums whose terms carry the
+ * scale 2^S (S = shift_log2; 0 in HAWKES_FP64); a row whose scaled rate falls
+ * below cmax 2^floor_log2 (cmax = the larger pair-term weight, c_bg or c_se)
+ * is recomputed exactly in float64 relative to its largest pair term instead.
+ * flags (device, n int32, or NULL) receives 1 for each recomputed row and 0
+ * otherwise.  Reads the workspace on `stream` after the evaluation and
+ * synchronizes the stream.  Host-side argument errors: EINVAL / EPARAM. */
+typedef struct {
+  int64_t flagged_rows;  /* rows recomputed by the float64 fix-up */
+  double shift_log2;     /* S */
+  double floor_log2;     /* recompute when lambda_n 2^S < cmax 2^floor_log2 */
+  double cmax;           /* max(c_bg, c_se) of Sec. 2.1's pair terms */
+} hawkes_diag_t;
+
+int hawkes_diagnostics(const void* ws /* device */, size_t ws_bytes, int64_t n, int d, int prec,
+                       const hawkes_params_t* p /* host */, void* stream, int32_t* flags /* device n, or NULL */,
+                       hawkes_diag_t* out /* host */);
+
 /* Per-event terms of the rate pass (Sec. 2.1) and the branching probability
  * used to colour events in the influenza application (Sec. 4.3): the
  * self-excitation share of the rate, xi(x_n, t_n) / lambda_n.  terms (device,

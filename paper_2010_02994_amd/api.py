@@ -137,6 +137,25 @@ def event_terms(x: torch.Tensor, t: torch.Tensor, params, prec="fp64", out: torc
     return terms, ll.value
 
 
+def diagnostics(x: torch.Tensor, t: torch.Tensor, params, prec="mixed"):
+    """Which rows the float64 fix-up recomputed in the last evaluation of
+    (x, t, params, prec) on the current stream (the cached workspace of
+    loglik / grad / grad_async / event_terms).  Returns (dict of the
+    diagnostics fields, flags as a numpy int32 array (N,)).  Synchronizes."""
+    x, t = _check_inputs(x, t)
+    n, d = x.shape
+    ws = workspace(n, d, prec, x.device)
+    flags = torch.empty(n, dtype=torch.int32, device=x.device)
+    out = _lib.HawkesDiag()
+    ps = params_struct(params)
+    st = _lib.lib().hawkes_diagnostics(ws.data_ptr(), ws.numel(), n, d, _prec(prec), ctypes.byref(ps),
+                                       _stream_ptr(x.device), flags.data_ptr(), ctypes.byref(out))
+    if st != _lib.OK:
+        raise HawkesError(st, "hawkes_diagnostics")
+    info = {k: getattr(out, k) for k, _ in _lib.HawkesDiag._fields_}
+    return info, flags.cpu().numpy()
+
+
 _mwg_ws: dict = {}
 
 

@@ -72,8 +72,9 @@ bool make_layout(int64_t n, int d, int prec, Layout& Lo) {
   Lo.off_rec = take(real * rw * (size_t)Lo.n_pad);
   Lo.off_first = take(sizeof(int) * (size_t)Lo.n_pad);
   Lo.off_ps = take(real * (size_t)Lo.n_pad);
-  Lo.off_prow = take(real * (size_t)Lo.items * std::max(6, d) * kBandRows);
-  Lo.off_pcol = take(real * (size_t)Lo.nb * std::max(3, d) * Lo.n_pad);
+  // row and column partial sums are float64 in both precisions
+  Lo.off_prow = take(sizeof(double) * (size_t)Lo.items * std::max(6, d) * kBandRows);
+  Lo.off_pcol = take(sizeof(double) * (size_t)Lo.nb * std::max(3, d) * Lo.n_pad);
   Lo.off_sums = take(sizeof(double) * 6 * (size_t)n);
   Lo.off_sigma = take(sizeof(double) * (size_t)n);
   Lo.off_flags = take(sizeof(int) * (size_t)n);
@@ -101,17 +102,17 @@ bool valid_params(const hawkes_params_t* p) {
 
 // Base-2 shift of the mixed pass.  In bandwidth units every accumulated
 // product is bounded: 2^(S-a r2) r2 <= 2^S 2/(e a ln 2) for a = mA or mG, and
-// 2^(S-w dt) dt <= 2^S/(e w ln 2); a tile sums at most 64 terms per row and a
-// column sum at most kBandRows terms.  S keeps all of them below 2^127 with
-// margin, and is at most 120.
+// 2^(S-w dt) dt <= 2^S/(e w ln 2); a float32 sum holds at most 32 such terms
+// (the micro-partials of the pair passes; everything beyond is float64).  S
+// keeps every float32 sum below 2^127 with margin, and is at most 120.
 static double shift_for(const KParams& k) {
   const double ln2 = std::log(2.0), e = std::exp(1.0);
   const double bound_r = 2.0 / (e * std::min((double)k.mA, (double)k.mG) * ln2);
   const double bound_t = 2.0 / (e * (double)k.mB * ln2);
   const double bound_w = 1.0 / (e * (double)k.mW * ln2);
   const double m = std::max({1.0, bound_r, bound_t, bound_w});
-  // headroom: 2^127 max float, minus log2 of the largest term count (a band's rows)
-  const double terms = std::ceil(std::log2((double)kBandRows));
+  // headroom: 2^127 max float, minus log2 of the largest float32 term count
+  const double terms = std::ceil(std::log2(32.0));
   return std::floor(std::min(kShiftMixed, 126.0 - terms - std::log2(m)));
 }
 
@@ -224,6 +225,10 @@ struct StageTimer {
   int used = 0;
 };
 static thread_local StageTimer* g_timer = nullptr;
+// Set while a call must create nothing (hawkes_grad_noalloc): only a side
+// stream already in the pool may be used, else the call runs on one stream.
+static thread_local bool g_no_create = false;
+void set_no_create(bool on) { g_no_create = on; }
 
 static inline void mark(hipStream_t s, int stage) {
   if (g_timer) {
@@ -371,7 +376,7 @@ int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const Batc
   if (grad && g_timer == nullptr && hipGetDevice(&dev) == hipSuccess) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     const bool capturing = hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
-    fk = fork_pool().take(dev, !capturing);
+    fk = fork_pool().take(dev, !capturing && !g_no_create);
   }
   const bool ok = mixed ? dispatch_d<true>(d, dev_reqs, nreq, g, grad, s, fk, one)
                         : dispatch_d<false>(d, dev_reqs, nreq, g, grad, s, fk, one);
@@ -418,9 +423,8 @@ int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_p
   return launch_batch(d, Lo.mixed, dev, 1, g, grad_x != nullptr, s, &desc);
 }
 
-static int run_sync(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
-                    size_t ws_bytes, void* stream, double* loglik, double* grad_x, double* grad_params,
-                    double* terms = nullptr) {
+int run_sync(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
+             size_t ws_bytes, void* stream, double* loglik, double* grad_x, double* grad_params, double* terms) {
   Layout Lo;
   if (!ws || !make_layout(n, d, prec, Lo)) return HAWKES_EINVAL;
   double* out8 = at<double>(ws, Lo.off_out8);
@@ -487,6 +491,29 @@ const char* hawkes_strerror(int status) {
 }
 
 const char* hawkes_version(void) { return "0.1.0"; }
+
+int hawkes_diagnostics(const void* ws, size_t ws_bytes, int64_t n, int d, int prec, const hawkes_params_t* p,
+                       void* stream, int32_t* flags, hawkes_diag_t* out) {
+  hawkes::Layout Lo;
+  if (!ws || !p || !out || !hawkes::make_layout(n, d, prec, Lo) || ws_bytes < Lo.total) return HAWKES_EINVAL;
+  if (!hawkes::valid_params(p)) return HAWKES_EPARAM;
+  const hawkes::KParams kp = hawkes::make_kparams(Lo, p);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const char* base = static_cast<const char*>(ws);
+  int count = 0;
+  if (hipMemcpyAsync(&count, base + Lo.off_status + sizeof(int) * hawkes::kStFlagCount, sizeof(int),
+                     hipMemcpyDeviceToHost, s) != hipSuccess)
+    return HAWKES_EDEVICE;
+  if (flags && hipMemcpyAsync(flags, base + Lo.off_flags, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice,
+                              s) != hipSuccess)
+    return HAWKES_EDEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return HAWKES_EDEVICE;
+  out->flagged_rows = count;
+  out->shift_log2 = (double)kp.S;
+  out->floor_log2 = kp.flag_floor;
+  out->cmax = kp.cmax;
+  return HAWKES_OK;
+}
 
 int hawkes_grad_timed(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec,
                       void* ws, size_t ws_bytes, void* stream, double* loglik, double* grad_x, double* grad_params,

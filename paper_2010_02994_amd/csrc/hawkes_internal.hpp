@@ -38,6 +38,13 @@ int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const Batc
 // grad_x is not null, the gradient pass) with no host synchronization.
 int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
               size_t ws_bytes, void* stream, double* out8, double* grad_x, double* terms = nullptr);
+// run_async, then the scalars to the host (stream synchronized).
+int run_sync(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
+             size_t ws_bytes, void* stream, double* loglik, double* grad_x, double* grad_params,
+             double* terms = nullptr);
+// While on (per host thread), gradient calls create no side stream or event:
+// they use one already pooled, or run every kernel on the caller's stream.
+void set_no_create(bool on);
 // A side stream and two events, from a per-device pool kept for the life of
 // the process.  A fork is held exclusively while a call enqueues and given
 // back afterwards.  allow_create = false (the stream is being captured into a

@@ -27,7 +27,7 @@ namespace hawkes {
 template <int D, bool MIX> struct Traits;
 template <int D> struct Traits<D, true> {
   using Real = float;
-  using ColT = float;
+  using ColT = double;   // partial sums stored outside a wave
   static constexpr int RW = ((D + 2 + 3) / 4) * 4;  // record words: coords, t, aux, pad
   struct alignas(16) Rec { float v[RW]; };
 };
@@ -560,9 +560,22 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ 
 // The float32 passes keep the symmetric (column) sums out of LDS atomics:
 // at step k of a 64-column tile, lane l pairs its rows with column (l + k) mod 64,
 // and the column accumulators rotate one lane per step with a DPP wave_rol:1
-// fused into the add (acc <- acc[lane + 1] + contribution).  After 64 steps
-// lane l holds the sums of column (l + 63) mod 64.  The tile's records sit in
-// LDS twice in a row, so the column read is lds[lane + k] with a constant offset.
+// fused into the add (acc <- acc[lane + 1] + contribution), so after step k
+// lane l holds the partial sum of column (l + k) mod 64.  The tile's records
+// sit in LDS twice in a row, so the column read is lds[lane + k] with a
+// constant offset.
+//
+// Float32 sums are micro-partials of at most 32 terms, folded into float64:
+// every kColSteps = 16 steps (16 steps x 2 rows = 32 terms) each lane adds
+// its rotating column accumulator, converted to float64, to its column's slot
+// of the wave's float64 LDS row (lanes hold distinct columns, so the adds do
+// not collide), and restarts it at zero; the row sums are folded into their
+// float64 accumulators every kRowFold = 32 steps.  Everything stored outside
+// the wave is float64.
+constexpr int kColSteps = 16;
+constexpr int kRowFold = 32;
+static_assert(kColSteps * kRowsPerLane <= 32 && kRowFold <= 32 && kRowFold % kColSteps == 0 && 64 % kRowFold == 0,
+              "float32 micro-partials hold at most 32 terms");
 
 __device__ __forceinline__ float rol1(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xf, 0xf, false));
@@ -570,86 +583,101 @@ __device__ __forceinline__ float rol1(float v) {
 
 template <int D, bool MASK, bool RU>
 __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const typename Traits<D, true>::Rec* __restrict__ cols,
-                                                 float* __restrict__ acc_w, int tile_base, const KParams& kp) {
+                                                 double* __restrict__ acc_w, int tile_base, const KParams& kp) {
   constexpr int R = kRowsPerLane;
   const int lane = threadIdx.x & 63;
   const float mA = kp.mA, mB = kp.mB, mG = kp.mG, mW = kp.mW, sh = kp.S;
   const typename Traits<D, true>::Rec* __restrict__ my = cols + lane;
-  float aK = 0.f, aR = 0.f, aU = 0.f;
   // The exponents of kRateExpSteps consecutive steps are formed first and
   // their exps issued back to back, so no exp result is consumed by the very
   // next instruction; the steps are then accumulated in order.
   constexpr int KS = kRateExpSteps;
-  constexpr int UN = HK_RATE_UNROLL / KS;
-#pragma unroll UN
-  for (int k0 = 0; k0 < 64; k0 += KS) {
-    float r2v[KS][R], dtv[KS][R], ebv[KS][R], esv[KS][R];
+  static_assert(kColSteps % KS == 0, "exp groups must not straddle a flush");
+  constexpr int UO = HK_RATE_UNROLL >= kRowFold ? HK_RATE_UNROLL / kRowFold : 1;
+#pragma unroll UO
+  for (int k2 = 0; k2 < 64; k2 += kRowFold) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const auto col = my[k0 + s];
+  for (int kc = 0; kc < kRowFold; kc += kColSteps) {
+    const int k1 = k2 + kc;
+    float aK = 0.f, aR = 0.f, aU = 0.f;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        float r2 = 0.f;
+    for (int kk = 0; kk < kColSteps; kk += KS) {
+      const int k0 = k1 + kk;
+      float r2v[KS][R], dtv[KS][R], ebv[KS][R], esv[KS][R];
 #pragma unroll
-        for (int q = 0; q < D; ++q) {
-          const float dx = S.x[r][q] - col.v[q];
-          r2 = q == 0 ? dx * dx : dx * dx + r2;
+      for (int s = 0; s < KS; ++s) {
+        const auto col = my[k0 + s];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          float r2 = 0.f;
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            const float dx = S.x[r][q] - col.v[q];
+            r2 = q == 0 ? dx * dx : dx * dx + r2;
+          }
+          const float dt = S.t[r] - col.v[D];
+          r2v[s][r] = r2;
+          dtv[s][r] = dt;
+          ebv[s][r] = __builtin_fmaf(-mB, dt * dt, __builtin_fmaf(-mA, r2, sh));
+          esv[s][r] = __builtin_fmaf(-mW, dt, __builtin_fmaf(-mG, r2, sh));
         }
-        const float dt = S.t[r] - col.v[D];
-        r2v[s][r] = r2;
-        dtv[s][r] = dt;
-        ebv[s][r] = __builtin_fmaf(-mB, dt * dt, __builtin_fmaf(-mA, r2, sh));
-        esv[s][r] = __builtin_fmaf(-mW, dt, __builtin_fmaf(-mG, r2, sh));
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          ebv[s][r] = __builtin_amdgcn_exp2f(ebv[s][r]);
+          esv[s][r] = __builtin_amdgcn_exp2f(esv[s][r]);
+        }
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int k = k0 + s;
+        float cK, cR, cU;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float r2 = r2v[s][r], dt = dtv[s][r], dt2 = dt * dt;
+          float eb = ebv[s][r], es = esv[s][r];
+          if (MASK) {
+            const bool act = (tile_base + ((lane + k) & 63)) < S.first[r];
+            eb = act ? eb : 0.f;
+            es = act ? es : 0.f;
+          }
+          S.a[r][0] += eb;
+          if (RU) {
+            S.a[r][1] = eb * r2 + S.a[r][1];
+            S.a[r][2] = eb * dt2 + S.a[r][2];
+          }
+          S.a[r][3] += es;
+          S.a[r][4] = es * r2 + S.a[r][4];
+          S.a[r][5] = es * dt + S.a[r][5];
+          // column contributions summed over this lane's rows (no "+ 0": a
+          // signed zero keeps the compiler from folding it)
+          cK = r == 0 ? eb : cK + eb;
+          if (RU) {
+            cR = r == 0 ? eb * r2 : eb * r2 + cR;
+            cU = r == 0 ? eb * dt2 : eb * dt2 + cU;
+          }
+        }
+        aK = rol1(aK) + cK;
+        if (RU) {
+          aR = rol1(aR) + cR;
+          aU = rol1(aU) + cU;
+        }
       }
     }
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        ebv[s][r] = __builtin_amdgcn_exp2f(ebv[s][r]);
-        esv[s][r] = __builtin_amdgcn_exp2f(esv[s][r]);
-      }
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int k = k0 + s;
-      float cK, cR, cU;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const float r2 = r2v[s][r], dt = dtv[s][r], dt2 = dt * dt;
-        float eb = ebv[s][r], es = esv[s][r];
-        if (MASK) {
-          const bool act = (tile_base + ((lane + k) & 63)) < S.first[r];
-          eb = act ? eb : 0.f;
-          es = act ? es : 0.f;
-        }
-        S.a[r][0] += eb;
-        if (RU) {
-          S.a[r][1] = eb * r2 + S.a[r][1];
-          S.a[r][2] = eb * dt2 + S.a[r][2];
-        }
-        S.a[r][3] += es;
-        S.a[r][4] = es * r2 + S.a[r][4];
-        S.a[r][5] = es * dt + S.a[r][5];
-        // column contributions summed over this lane's rows (no "+ 0": a
-        // signed zero keeps the compiler from folding it)
-        cK = r == 0 ? eb : cK + eb;
-        if (RU) {
-          cR = r == 0 ? eb * r2 : eb * r2 + cR;
-          cU = r == 0 ? eb * dt2 : eb * dt2 + cU;
-        }
-      }
-      aK = rol1(aK) + cK;
-      if (RU) {
-        aR = rol1(aR) + cR;
-        aU = rol1(aU) + cU;
-      }
-    }
+    // column flush: this lane now holds column (lane + k1 + kColSteps - 1) mod 64
+    const int c = (lane + k1 + kColSteps - 1) & 63;
+    acc_w[0 * 64 + c] += (double)aK;
+    if (RU) { acc_w[1 * 64 + c] += (double)aR; acc_w[2 * 64 + c] += (double)aU; }
   }
-  const int c = (lane + 63) & 63;
-  acc_w[0 * 64 + c] = aK;
-  if (RU) {
-    acc_w[1 * 64 + c] = aR;
-    acc_w[2 * 64 + c] = aU;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      if (!RU && (q == 1 || q == 2)) continue;
+      S.acc[r][q] += (double)S.a[r][q];
+      S.a[r][q] = 0.f;
+    }
   }
 }
 
@@ -661,7 +689,7 @@ template <int D, bool RU>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(rate_waves(D, RU)))) k_pass1_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
   using Rec = typename Traits<D, true>::Rec;
   using Real = float;
-  using ColT = float;
+  using ColT = double;
   constexpr int R = kRowsPerLane;
   constexpr int NQ = RU ? 3 : 1;   // column sums
   constexpr int QR = RU ? 6 : 4;   // row sums stored per item
@@ -717,19 +745,16 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(r
       pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
     }
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
-    if (tile_culled<D, true>(t_row0, &s_rec[buf][0], tile, kp)) {
-      // the tile adds exactly zero: its column sums are zero
+    // the wave's float64 column slots start at zero (a culled tile adds
+    // exactly zero and leaves them so)
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) s_acc[buf][wave][q][lane] = 0.f;
+    for (int q = 0; q < NQ; ++q) s_acc[buf][wave][q][lane] = 0.0;
+    if (tile_culled<D, true>(t_row0, &s_rec[buf][0], tile, kp)) {
     } else if (full) {
       pass1_tile_mixed<D, false, RU>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
     } else {
       pass1_tile_mixed<D, true, RU>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int q = 0; q < 6; ++q) { S.acc[r][q] += (double)S.a[r][q]; S.a[r][q] = 0.f; }
   }
   __syncthreads();
   for (int e = threadIdx.x; e < NQ * kTile; e += kThreads) {
@@ -746,90 +771,108 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(r
 #pragma unroll
     for (int q = 0; q < QR; ++q) {
       const int src = RU ? q : (q == 0 ? 0 : q + 2);   // without RU: K, J, V, W
-      glb(static_cast<float*>(rq.prow))[((int64_t)item * QR + q) * kBandRows + lr] = (float)S.acc[r][src];
+      glb(static_cast<double*>(rq.prow))[((int64_t)item * QR + q) * kBandRows + lr] = S.acc[r][src];
     }
   }
 }
 
 template <int D, bool MASK>
 __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const typename Traits<D, true>::Rec* __restrict__ cols,
-                                                 float* __restrict__ acc_w, int tile_base, const KParams& kp) {
+                                                 double* __restrict__ acc_w, int tile_base, const KParams& kp) {
   constexpr int R = kRowsPerLane;
   const int lane = threadIdx.x & 63;
   const float mA = kp.mA, mB = kp.mB, mG = kp.mG, mW = kp.mW, sh = kp.S;
   const typename Traits<D, true>::Rec* __restrict__ my = cols + lane;
-  float ag[D];
-#pragma unroll
-  for (int q = 0; q < D; ++q) ag[q] = 0.f;
   // exponents of kGradExpSteps steps first, exps back to back, then the
   // steps in order (as in the rate pass)
   constexpr int KS = kGradExpSteps;
-  constexpr int UN = HK_GRAD_UNROLL / KS;
-#pragma unroll UN
-  for (int k0 = 0; k0 < 64; k0 += KS) {
-    float dx[KS][R][D], r2[KS][R], dt[KS][R], eb[KS][R], es[KS][R], pbj[KS];
+  static_assert(kColSteps % KS == 0, "exp groups must not straddle a flush");
+  constexpr int UO = HK_GRAD_UNROLL >= kRowFold ? HK_GRAD_UNROLL / kRowFold : 1;
+#pragma unroll UO
+  for (int k2 = 0; k2 < 64; k2 += kRowFold) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const auto col = my[k0 + s];
-      pbj[s] = col.v[D + 1];
+  for (int kc = 0; kc < kRowFold; kc += kColSteps) {
+    const int k1 = k2 + kc;
+    float ag[D];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
+    for (int q = 0; q < D; ++q) ag[q] = 0.f;
 #pragma unroll
-        for (int q = 0; q < D; ++q) {
-          dx[s][r][q] = S.x[r][q] - col.v[q];
-          r2[s][r] = q == 0 ? dx[s][r][q] * dx[s][r][q] : dx[s][r][q] * dx[s][r][q] + r2[s][r];
+    for (int kk = 0; kk < kColSteps; kk += KS) {
+      const int k0 = k1 + kk;
+      float dx[KS][R][D], r2[KS][R], dt[KS][R], eb[KS][R], es[KS][R], pbj[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const auto col = my[k0 + s];
+        pbj[s] = col.v[D + 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            dx[s][r][q] = S.x[r][q] - col.v[q];
+            r2[s][r] = q == 0 ? dx[s][r][q] * dx[s][r][q] : dx[s][r][q] * dx[s][r][q] + r2[s][r];
+          }
+          dt[s][r] = S.t[r] - col.v[D];
+          eb[s][r] = __builtin_fmaf(-mB, dt[s][r] * dt[s][r], __builtin_fmaf(-mA, r2[s][r], sh));
+          es[s][r] = __builtin_fmaf(-mW, dt[s][r], __builtin_fmaf(-mG, r2[s][r], sh));
         }
-        dt[s][r] = S.t[r] - col.v[D];
-        eb[s][r] = __builtin_fmaf(-mB, dt[s][r] * dt[s][r], __builtin_fmaf(-mA, r2[s][r], sh));
-        es[s][r] = __builtin_fmaf(-mW, dt[s][r], __builtin_fmaf(-mG, r2[s][r], sh));
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          eb[s][r] = __builtin_amdgcn_exp2f(eb[s][r]);
+          es[s][r] = __builtin_amdgcn_exp2f(es[s][r]);
+        }
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int k = k0 + s;
+        float cgr[D];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          float ebr = eb[s][r], esr = es[s][r];
+          if (MASK) {
+            const bool act = (tile_base + ((lane + k) & 63)) < S.first[r];
+            ebr = act ? ebr : 0.f;
+            esr = act ? esr : 0.f;
+          }
+          // background weight of the pair with both endpoints' 1/lambda; its
+          // r^2 and dt^2 moments give the rate pass's R and U terms of the
+          // tau_x and tau_t gradients
+          const float wb = ebr * (S.pb[r] + pbj[s]);
+          const float coef = esr * S.ps[r] + wb;
+          S.mom[0] = wb * r2[s][r] + S.mom[0];
+          S.mom[1] = wb * (dt[s][r] * dt[s][r]) + S.mom[1];
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            S.g[r][q] = -coef * dx[s][r][q] + S.g[r][q];
+            cgr[q] = r == 0 ? coef * dx[s][r][q] : coef * dx[s][r][q] + cgr[q];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < D; ++q) ag[q] = rol1(ag[q]) + cgr[q];
       }
     }
+    // column flush: this lane now holds column (lane + k1 + kColSteps - 1) mod 64
+    const int c = (lane + k1 + kColSteps - 1) & 63;
 #pragma unroll
-    for (int s = 0; s < KS; ++s)
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        eb[s][r] = __builtin_amdgcn_exp2f(eb[s][r]);
-        es[s][r] = __builtin_amdgcn_exp2f(es[s][r]);
-      }
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int k = k0 + s;
-      float cgr[D];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        float ebr = eb[s][r], esr = es[s][r];
-        if (MASK) {
-          const bool act = (tile_base + ((lane + k) & 63)) < S.first[r];
-          ebr = act ? ebr : 0.f;
-          esr = act ? esr : 0.f;
-        }
-        // background weight of the pair with both endpoints' 1/lambda; its
-        // r^2 and dt^2 moments give the rate pass's R and U terms of the
-        // tau_x and tau_t gradients
-        const float wb = ebr * (S.pb[r] + pbj[s]);
-        const float coef = esr * S.ps[r] + wb;
-        S.mom[0] = wb * r2[s][r] + S.mom[0];
-        S.mom[1] = wb * (dt[s][r] * dt[s][r]) + S.mom[1];
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
-          S.g[r][q] = -coef * dx[s][r][q] + S.g[r][q];
-          cgr[q] = r == 0 ? coef * dx[s][r][q] : coef * dx[s][r][q] + cgr[q];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < D; ++q) ag[q] = rol1(ag[q]) + cgr[q];
-    }
+    for (int q = 0; q < D; ++q) acc_w[q * 64 + c] += (double)ag[q];
+    // the moments hold 2 rows x kColSteps terms: fold them at every flush
+    S.momd[0] += (double)S.mom[0];
+    S.momd[1] += (double)S.mom[1];
+    S.mom[0] = S.mom[1] = 0.f;
   }
-  const int c = (lane + 63) & 63;
 #pragma unroll
-  for (int q = 0; q < D; ++q) acc_w[q * 64 + c] = ag[q];
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int q = 0; q < D; ++q) { S.acc[r][q] += (double)S.g[r][q]; S.g[r][q] = 0.f; }
+  }
 }
 
 template <int D>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(grad_waves(D)))) k_pass2_mixed(const ReqDesc* __restrict__ reqs, int nreq) {
   using Rec = typename Traits<D, true>::Rec;
   using Real = float;
-  using ColT = float;
+  using ColT = double;
   constexpr int R = kRowsPerLane;
   constexpr int NQ = D;
   __shared__ Rec s_rec[2][2 * kTile];
@@ -887,22 +930,16 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(g
       pcol[((int64_t)band * NQ + q) * kp.n_pad + (tile - 1) * kTile + c] = s;
     }
     const bool full = !partial_band && (tile + 1) * kTile <= first_min;
-    if (tile_culled<D, true>(t_row0, &s_rec[buf][0], tile, kp)) {
-      // the tile adds exactly zero: its column sums are zero
+    // the wave's float64 column slots start at zero (a culled tile adds
+    // exactly zero and leaves them so)
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) s_acc[buf][wave][q][lane] = 0.f;
+    for (int q = 0; q < NQ; ++q) s_acc[buf][wave][q][lane] = 0.0;
+    if (tile_culled<D, true>(t_row0, &s_rec[buf][0], tile, kp)) {
     } else if (full) {
       pass2_tile_mixed<D, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
     } else {
       pass2_tile_mixed<D, true>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int q = 0; q < D; ++q) { S.acc[r][q] += (double)S.g[r][q]; S.g[r][q] = 0.f; }
-    S.momd[0] += (double)S.mom[0];
-    S.momd[1] += (double)S.mom[1];
-    S.mom[0] = S.mom[1] = 0.f;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < NQ * kTile; e += kThreads) {
@@ -918,7 +955,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(g
     const int lr = wave * 64 * R + r * 64 + lane;
 #pragma unroll
     for (int q = 0; q < D; ++q)
-      glb(static_cast<float*>(rq.prow))[((int64_t)item * D + q) * kBandRows + lr] = (float)S.acc[r][q];
+      glb(static_cast<double*>(rq.prow))[((int64_t)item * D + q) * kBandRows + lr] = S.acc[r][q];
   }
   // the item's two moment sums, fixed-order over the workgroup
   double mom[2] = {S.momd[0], S.momd[1]};
@@ -952,7 +989,7 @@ __device__ __forceinline__ double quad_sum(double v) {
 
 template <int D, bool MIX>
 __global__ void __launch_bounds__(kRedThreads) k_reduce1(const ReqDesc* __restrict__ reqs, int nreq) {
-  using ColT = typename std::conditional<MIX, float, double>::type;
+  using ColT = double;   // partials are float64 in both precisions
   using Real = typename Traits<D, MIX>::Real;
   using Rec = typename Traits<D, MIX>::Rec;
   __shared__ int s_cnt[kRedThreads / 64];
@@ -1348,7 +1385,7 @@ __global__ void __launch_bounds__(kEvBlock) k_fix2(const ReqDesc* __restrict__ r
 // lanes per event as in k_reduce1).
 template <int D, bool MIX>
 __global__ void __launch_bounds__(kRedThreads) k_reduce2(const ReqDesc* __restrict__ reqs, int nreq) {
-  using ColT = typename std::conditional<MIX, float, double>::type;
+  using ColT = double;   // partials are float64 in both precisions
   const int rid = find_req(reqs, nreq, blockIdx.x, 1);
   const ReqDesc& rq = reqs[rid];
   const KParams& kp = rq.kp;

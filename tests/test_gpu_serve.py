@@ -8,7 +8,7 @@ import torch
 import oracle
 from paper_2010_02994_amd import _lib, api, workloads as W
 from paper_2010_02994_amd.serve import Server
-from tests.gpu_util import check, say
+from tests.gpu_util import check, oracle_ref, say
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -66,10 +66,10 @@ def test_alone_vs_mix_bitwise_and_direct_call(data):
         assert ll == a[1] and np.array_equal(gp, a[2]) and np.array_equal(gx.cpu().numpy(), a[3]), (k, p)
     for k in (0, 3):
         w = data[k][0]
-        st_, ll_ref, gx_ref, gp_ref = oracle.loglik_grad(w.x, w.t, w.params, threads=True)
+        ref = oracle_ref(w.x, w.t, w.params)
         for p in ("mixed", "fp64"):
             j = reqs.index((k, p))
-            check(p, alone[j][1], alone[j][3], alone[j][2], ll_ref, gx_ref, gp_ref, w.params, w.n, label=f"serve{k}")
+            check(p, (alone[j][1], alone[j][3], alone[j][2]), ref, w.params, label=f"serve{k}")
 
 
 def test_requests_without_gradient_match_the_direct_call(data):
