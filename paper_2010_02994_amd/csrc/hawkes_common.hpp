@@ -26,9 +26,9 @@ namespace hawkes {
 #define HK_GRAD_EXP_STEPS 1
 #endif
 // Column steps of a tile's 64-step sweep unrolled per loop trip in the mixed
-// rate and gradient passes (16 and 32 measured fastest on gfx950).
+// rate and gradient passes (32: one trip per float32 row fold).
 #ifndef HK_RATE_UNROLL
-#define HK_RATE_UNROLL 16
+#define HK_RATE_UNROLL 32
 #endif
 #ifndef HK_GRAD_UNROLL
 #define HK_GRAD_UNROLL 32

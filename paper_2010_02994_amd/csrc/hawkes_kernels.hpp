@@ -74,6 +74,8 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // in this pass's arithmetic.  Records are time-sorted, so the band's first row
 // (t_row0, read once per work item) and the tile's last column (read from the
 // tile's records already staged in LDS) bound every pair's time difference.
+// Mixed records hold times relative to their own tile's first event; there
+// t_row0 is the band's first row relative to the column tile's first event.
 template <int D, bool MIX, typename Real, typename Rec>
 __device__ __forceinline__ bool tile_culled(Real t_row0, const Rec* tile_recs, int tile, const KParams& kp) {
   if (!kp.cull) return false;
@@ -82,6 +84,16 @@ __device__ __forceinline__ bool tile_culled(Real t_row0, const Rec* tile_recs, i
   if constexpr (MIX) c = (float)t_row0 - (float)tile_recs[last].v[D] > kp.cull_dtf;
   else c = (double)t_row0 - (double)tile_recs[last].v[D] > kp.cull_dt;
   return uni(c ? 1 : 0) != 0;
+}
+
+// Mixed records: an event's time is stored relative to the first event of its
+// own column tile of kTile events (so the float32 offsets span one tile's time
+// range), and for each column tile the rows' times are re-expressed relative to
+// that tile's first event in float64 and rounded once: a pair's time
+// difference then carries an absolute rounding error of about 2^-24 times
+// (|dt| + the tile's time span), whatever the length of the window.
+__device__ __forceinline__ double tile_origin(const double* t, int tile) {
+  return glb(t)[(int64_t)tile * kTile];
 }
 
 // Which request of a batched launch owns block `blk`: the last request whose
@@ -201,7 +213,8 @@ __global__ void __launch_bounds__(kEvBlock) k_pack(const ReqDesc* __restrict__ r
       const double v = glb(rq.x)[(int64_t)i * D + k];
       rr.v[k] = MIX ? Real((v - glb(rq.dconst)[1 + k]) * rq.kp.inv_tx) : Real(v);
     }
-    rr.v[D] = MIX ? Real((ti - glb(rq.dconst)[1 + kMaxD]) * rq.kp.inv_tt) : Real(ti);
+    // mixed: time relative to the first event of the event's column tile
+    rr.v[D] = MIX ? Real((ti - t[(int64_t)(i / kTile) * kTile]) * rq.kp.inv_tt) : Real(ti);
     // first index with time ti: i itself unless the previous event ties
     // (then a lower_bound of ti in t[0..i], a chain of dependent loads that
     // only tied events pay)
@@ -254,7 +267,7 @@ template <int D, bool MIX>
 struct Pass1Rows {
   using Real = typename Traits<D, MIX>::Real;
   static constexpr int R = kRowsPerLane;
-  Real x[R][D], t[R];
+  Real x[R][D], t[R];   // mixed: t is relative to the current column tile's first event
   int first[R];
   Real a[R][6];        // per-tile partials (float32 in mixed, the running sums in float64)
   double acc[R][6];    // float64 running sums (mixed path only)
@@ -411,7 +424,7 @@ template <int D, bool MIX>
 struct Pass2Rows {
   using Real = typename Traits<D, MIX>::Real;
   static constexpr int R = kRowsPerLane;
-  Real x[R][D], t[R], pb[R], ps[R];
+  Real x[R][D], t[R], pb[R], ps[R];   // mixed: t is relative to the current column tile's first event
   int first[R];
   Real g[R][D];
   Real mom[2];        // mixed: per-tile sums of w r^2 and w dt^2 (w = background pair weight)
@@ -568,10 +581,11 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ 
 // Float32 sums are micro-partials of at most 32 terms, folded into float64:
 // every kColSteps = 16 steps (16 steps x 2 rows = 32 terms) each lane adds
 // its rotating column accumulator, converted to float64, to its column's slot
-// of the wave's float64 LDS row (lanes hold distinct columns, so the adds do
-// not collide), and restarts it at zero; the row sums are folded into their
-// float64 accumulators every kRowFold = 32 steps.  Everything stored outside
-// the wave is float64.
+// of the wave's float64 LDS row with an LDS add (lanes hold distinct columns
+// and a wave's LDS operations run in program order, so each slot receives its
+// four adds in a fixed order), and restarts it at zero; the row sums are
+// folded into their float64 accumulators every kRowFold = 32 steps.
+// Everything stored outside the wave is float64.
 constexpr int kColSteps = 16;
 constexpr int kRowFold = 32;
 static_assert(kColSteps * kRowsPerLane <= 32 && kRowFold <= 32 && kRowFold % kColSteps == 0 && 64 % kRowFold == 0,
@@ -594,9 +608,10 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
   constexpr int KS = kRateExpSteps;
   static_assert(kColSteps % KS == 0, "exp groups must not straddle a flush");
   constexpr int UO = HK_RATE_UNROLL >= kRowFold ? HK_RATE_UNROLL / kRowFold : 1;
+  constexpr int UC = HK_RATE_UNROLL >= kRowFold ? kRowFold / kColSteps : 1;
 #pragma unroll UO
   for (int k2 = 0; k2 < 64; k2 += kRowFold) {
-#pragma unroll
+#pragma unroll UC
   for (int kc = 0; kc < kRowFold; kc += kColSteps) {
     const int k1 = k2 + kc;
     float aK = 0.f, aR = 0.f, aU = 0.f;
@@ -667,8 +682,8 @@ __device__ __forceinline__ void pass1_tile_mixed(Pass1Rows<D, true>& S, const ty
     }
     // column flush: this lane now holds column (lane + k1 + kColSteps - 1) mod 64
     const int c = (lane + k1 + kColSteps - 1) & 63;
-    acc_w[0 * 64 + c] += (double)aK;
-    if (RU) { acc_w[1 * 64 + c] += (double)aR; acc_w[2 * 64 + c] += (double)aU; }
+    atomicAdd(&acc_w[0 * 64 + c], (double)aK);
+    if (RU) { atomicAdd(&acc_w[1 * 64 + c], (double)aR); atomicAdd(&acc_w[2 * 64 + c], (double)aU); }
   }
 #pragma unroll
   for (int r = 0; r < R; ++r)
@@ -694,6 +709,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(r
   constexpr int NQ = RU ? 3 : 1;   // column sums
   constexpr int QR = RU ? 6 : 4;   // row sums stored per item
   __shared__ Rec s_rec[2][2 * kTile];
+  __shared__ double s_trow[R * kThreads];   // the rows' event times
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
   const int rid = find_req(reqs, nreq, blockIdx.x, 0);
   const ReqDesc& rq = reqs[rid];
@@ -712,7 +728,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(r
   const int tile1 = min(tile0 + kp.L, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
   const int first_min = uni(first[row_base]);
-  const auto t_row0 = rec[row_base].v[D];   // the band's first row (culling)
+  const double t_row0 = glb(rq.t)[row_base];   // the band's first row (culling)
 
   Pass1Rows<D, true> S;
 #pragma unroll
@@ -723,7 +739,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(r
     for (int q = 0; q < (int)(sizeof(Rec) / sizeof(rr.v[0])); ++q) rr.v[q] = rec[gi].v[q];
 #pragma unroll
     for (int q = 0; q < D; ++q) S.x[r][q] = rr.v[q];
-    S.t[r] = rr.v[D];
+    s_trow[r * kThreads + threadIdx.x] = glb(rq.t)[gi < kp.n ? gi : kp.n - 1];   // own slots: no barrier
     S.first[r] = first[gi];
 #pragma unroll
     for (int q = 0; q < 6; ++q) { S.a[r][q] = Real(0); S.acc[r][q] = 0.0; }
@@ -749,7 +765,11 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(r
     // exactly zero and leaves them so)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) s_acc[buf][wave][q][lane] = 0.0;
-    if (tile_culled<D, true>(t_row0, &s_rec[buf][0], tile, kp)) {
+    // row times relative to this column tile's first event
+    const double t_tile = tile_origin(rq.t, tile);
+#pragma unroll
+    for (int r = 0; r < R; ++r) S.t[r] = (float)((s_trow[r * kThreads + threadIdx.x] - t_tile) * kp.inv_tt);
+    if (tile_culled<D, true>((float)((t_row0 - t_tile) * kp.inv_tt), &s_rec[buf][0], tile, kp)) {
     } else if (full) {
       pass1_tile_mixed<D, false, RU>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
     } else {
@@ -788,9 +808,10 @@ __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const ty
   constexpr int KS = kGradExpSteps;
   static_assert(kColSteps % KS == 0, "exp groups must not straddle a flush");
   constexpr int UO = HK_GRAD_UNROLL >= kRowFold ? HK_GRAD_UNROLL / kRowFold : 1;
+  constexpr int UC = HK_GRAD_UNROLL >= kRowFold ? kRowFold / kColSteps : 1;
 #pragma unroll UO
   for (int k2 = 0; k2 < 64; k2 += kRowFold) {
-#pragma unroll
+#pragma unroll UC
   for (int kc = 0; kc < kRowFold; kc += kColSteps) {
     const int k1 = k2 + kc;
     float ag[D];
@@ -855,7 +876,7 @@ __device__ __forceinline__ void pass2_tile_mixed(Pass2Rows<D, true>& S, const ty
     // column flush: this lane now holds column (lane + k1 + kColSteps - 1) mod 64
     const int c = (lane + k1 + kColSteps - 1) & 63;
 #pragma unroll
-    for (int q = 0; q < D; ++q) acc_w[q * 64 + c] += (double)ag[q];
+    for (int q = 0; q < D; ++q) atomicAdd(&acc_w[q * 64 + c], (double)ag[q]);
     // the moments hold 2 rows x kColSteps terms: fold them at every flush
     S.momd[0] += (double)S.mom[0];
     S.momd[1] += (double)S.mom[1];
@@ -876,6 +897,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(g
   constexpr int R = kRowsPerLane;
   constexpr int NQ = D;
   __shared__ Rec s_rec[2][2 * kTile];
+  __shared__ double s_trow[R * kThreads];   // the rows' event times
   __shared__ ColT s_acc[2][kWaves][NQ][kTile];
   __shared__ double s_red[2 * kThreads];
   const int rid = find_req(reqs, nreq, blockIdx.x, 0);
@@ -895,7 +917,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(g
   const int tile1 = min(tile0 + kp.L, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
   const int first_min = uni(first[row_base]);
-  const auto t_row0 = rec[row_base].v[D];   // the band's first row (culling)
+  const double t_row0 = glb(rq.t)[row_base];   // the band's first row (culling)
 
   Pass2Rows<D, true> S;
   S.mom[0] = S.mom[1] = 0.f;
@@ -908,7 +930,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(g
     for (int q = 0; q < (int)(sizeof(Rec) / sizeof(rr.v[0])); ++q) rr.v[q] = rec[gi].v[q];
 #pragma unroll
     for (int q = 0; q < D; ++q) { S.x[r][q] = rr.v[q]; S.g[r][q] = Real(0); S.acc[r][q] = 0.0; }
-    S.t[r] = rr.v[D];
+    s_trow[r * kThreads + threadIdx.x] = glb(rq.t)[gi < kp.n ? gi : kp.n - 1];   // own slots: no barrier
     S.pb[r] = rr.v[D + 1];
     S.ps[r] = glb(static_cast<const Real*>(rq.ps))[gi];
     S.first[r] = first[gi];
@@ -934,7 +956,11 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(g
     // exactly zero and leaves them so)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) s_acc[buf][wave][q][lane] = 0.0;
-    if (tile_culled<D, true>(t_row0, &s_rec[buf][0], tile, kp)) {
+    // row times relative to this column tile's first event
+    const double t_tile = tile_origin(rq.t, tile);
+#pragma unroll
+    for (int r = 0; r < R; ++r) S.t[r] = (float)((s_trow[r * kThreads + threadIdx.x] - t_tile) * kp.inv_tt);
+    if (tile_culled<D, true>((float)((t_row0 - t_tile) * kp.inv_tt), &s_rec[buf][0], tile, kp)) {
     } else if (full) {
       pass2_tile_mixed<D, false>(S, s_rec[buf], &s_acc[buf][wave][0][0], tile * kTile, kp);
     } else {

@@ -15,12 +15,15 @@ Metrics (each against the float64 oracle):
 Tolerances: float64 1e-10 for every metric.  Mixed: 1e-5 (ll) and 1e-4 (gx,
 gp) as the precision contract states; for the per-row and per-component
 metrics, which no averaging over rows helps, the bound follows from the
-float32 pair arithmetic: coordinates are rounded to float32 in units of the
-bandwidths, offsets from the data's centre, so with coordinates spanning up to
-~250 bandwidths (the 500 km box) a pair term can carry a relative error up to
-~1e-4 (ulp(250) = 1.5e-5 in each difference, times the exponent's slope); a
-row's or a component's error is a weighted mean of its terms' errors, so it
-stays below 3e-4 of its scale."""
+float32 pair arithmetic: locations are rounded to float32 in units of the
+spatial bandwidth, as offsets from the data's centre, so with locations
+spanning up to ~250 bandwidths (the 500 km box) each coordinate difference
+carries an absolute error up to ulp(250) = 1.5e-5 bandwidths and a pair term a
+relative error up to ~1e-4 (that error times the exponent's slope, ~2|dx|, at
+the distances where terms matter); times are offsets from each column tile's
+first event, exact to ~2^-24 of the pair's time difference.  A row's or a
+component's error is a weighted mean of its terms' errors, so it stays below
+3e-4 of its scale."""
 import dataclasses
 import sys
 
