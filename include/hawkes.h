@@ -141,6 +141,25 @@ int hawkes_diagnostics(const void* ws /* device */, size_t ws_bytes, int64_t n, 
                        const hawkes_params_t* p /* host */, void* stream, int32_t* flags /* device n, or NULL */,
                        hawkes_diag_t* out /* host */);
 
+/* hawkes_grad for callers that cannot allocate device memory: code running
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The workspace is a library-owned static device array of
+ * HAWKES_NOALLOC_SCRATCH_BYTES per GPU (each GPU the library runs on holds
+ * its own copy until the process ends), so the call allocates nothing and
+ * creates no stream: the fix-up and finalize kernels share `stream` unless
+ * a side stream is already pooled.  Limit: hawkes_workspace_bytes(n, d,
+ * prec) <= HAWKES_NOALLOC_SCRATCH_BYTES (about n <= 18,000 at d = 2), else
+ * HAWKES_ENOMEM and nothing runs.  Every call on one GPU shares its array,
+ * which keeps the last call's contents (each call writes every part it
+ * reads), so calls that overlap on one GPU -- from two threads, or on two
+ * streams without ordering -- race and must not be issued.  Arguments,
+ * outputs, synchronization and results as hawkes_grad (bitwise equal to
+ * hawkes_grad with its own workspace). */
+#define HAWKES_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hawkes_grad_noalloc(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p /* host */,
+                        int prec, void* stream, double* loglik /* host or NULL */, double* grad_x /* device */,
+                        double* grad_params /* host or NULL */);
+
 /* Per-event terms of the rate pass (Sec. 2.1) and the branching probability
  * used to colour events in the influenza application (Sec. 4.3): the
  * self-excitation share of the rate, xi(x_n, t_n) / lambda_n.  terms (device,

@@ -52,6 +52,7 @@ def lib():
                                         ctypes.POINTER(ctypes.c_float)]
         L.hawkes_event_terms.argtypes = [dp, dp, i64, ci, pp, ci, vp, ctypes.c_size_t, vp, dp, hd]
         L.hawkes_diagnostics.argtypes = [vp, ctypes.c_size_t, i64, ci, ci, pp, vp, vp, ctypes.POINTER(HawkesDiag)]
+        L.hawkes_grad_noalloc.argtypes = [dp, dp, i64, ci, pp, ci, vp, hd, dp, hd]
         L.hawkes_mwg_workspace_bytes.argtypes = [i64]
         L.hawkes_mwg_workspace_bytes.restype = ctypes.c_size_t
         L.hawkes_mwg_step.argtypes = [dp, dp, i64, ci, pp, dp, vp, dp, i64, dp, vp, ctypes.c_size_t, vp, dp]
@@ -65,7 +66,7 @@ def lib():
                                            ci, dp, dp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp, dp, ci, dp,
                                            dp]
         for f in (L.hawkes_loglik, L.hawkes_grad, L.hawkes_grad_async, L.hawkes_grad_timed, L.hawkes_event_terms,
-                  L.hawkes_diagnostics,
+                  L.hawkes_diagnostics, L.hawkes_grad_noalloc,
                   L.hawkes_mwg_step, L.hawkes_loglik_reweight, L.hawkes_leapfrog, L.hawkes_bmds,
                   L.hawkes_leapfrog_bmds):
             f.restype = ci

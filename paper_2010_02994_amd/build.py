@@ -31,7 +31,7 @@ def _run(cmd):
 
 
 def build_library() -> str:
-    srcs = [os.path.join(CSRC, f) for f in ("hawkes.hip", "serve.hip", "mwg.hip", "hmc.hip", "bmds.hip")]
+    srcs = [os.path.join(CSRC, f) for f in ("hawkes.hip", "serve.hip", "mwg.hip", "hmc.hip", "bmds.hip", "noalloc.hip")]
     tmp = LIB + ".tmp"
     _run([_hipcc(), *HIPFLAGS, "-fPIC", "-shared", "-lpthread", *srcs, "-o", tmp])
     os.replace(tmp, LIB)

@@ -49,3 +49,15 @@ def test_host_argument_errors():
 @pytest.mark.parametrize("code", [0, -1, -2, -3, -4, -5, -6, -7, -8, 1, 99])
 def test_strerror(code):
     assert isinstance(_lib.strerror(code), str) and len(_lib.strerror(code)) >= 2
+
+
+def test_noalloc_rejects_sizes_beyond_its_scratch_on_the_host():
+    """hawkes_grad_noalloc refuses (n, d, prec) whose workspace exceeds the
+    static scratch before any device call (fake pointers are never touched)."""
+    L = _lib.lib()
+    p = _lib.HawkesParams(0.5, 1, 10, 0.3, 0.1, 2.0)
+    fake = ctypes.c_void_p(0x1000)
+    assert L.hawkes_workspace_bytes(50000, 2, 1) > 64 << 20
+    assert L.hawkes_grad_noalloc(fake, fake, 50000, 2, ctypes.byref(p), 1, None, None, fake, None) == _lib.ENOMEM
+    assert L.hawkes_grad_noalloc(fake, fake, 1, 2, ctypes.byref(p), 1, None, None, fake, None) == _lib.EINVAL
+    assert L.hawkes_grad_noalloc(fake, fake, 100, 2, ctypes.byref(p), 1, None, None, None, None) == _lib.EINVAL
