@@ -67,17 +67,21 @@ def measured_traffic(kernel_prefix: str, workload: str):
     return None
 
 
-def pass_work(d: int, which: str, prec: str = "mixed"):
-    """Algorithmic work per unordered pair: (FLOPs with FMA = 2, exps).
-    Float64 path -- rate pass: differences (D+1), r^2 (2D-1), dt^2 (1), two
-    exponents (8), nine accumulations (15); gradient pass: recompute (3D+9),
-    weights (6), two-sided scatter (4D).  Mixed gradient calls move the two
-    background moments (r^2 and dt^2 sums, row and column: 8) out of the rate
-    pass (3D+16) and form their gradient terms in the gradient pass as two
-    weighted sums (4): 7D+19."""
-    if prec.startswith("mixed"):
-        return (3 * d + 16, 2) if which == "pass1" else (7 * d + 19, 2)
+def pass_work(d: int, which: str):
+    """Algorithmic work per unordered pair (FLOPs with FMA = 2, exps), the
+    method's minimum: rate pass -- differences (D+1), r^2 (2D-1), dt^2 (1), two
+    exponents (8), nine accumulations (15): 3D+24 and 2 exps; gradient pass --
+    recompute (3D+9), weights (6), two-sided scatter (4D): 7D+15 and 2 exps.
+    The roofline is priced with these counts for both precisions."""
     return (3 * d + 24, 2) if which == "pass1" else (7 * d + 15, 2)
+
+
+def pass_work_resplit(d: int, which: str):
+    """The same total work as split by a mixed gradient call, which moves the
+    two background moments (r^2 and dt^2 sums, row and column: 8 FLOPs) out of
+    the rate pass and forms their gradient terms in the gradient pass as two
+    weighted sums (4 FLOPs): 3D+16 and 7D+19.  Reported beside the roofline."""
+    return (3 * d + 16, 2) if which == "pass1" else (7 * d + 19, 2)
 
 
 def main():
@@ -89,7 +93,8 @@ def main():
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="single-core oracle seconds the CPU baseline's sample is sized for")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests per precision in the serving run (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -126,11 +131,14 @@ def main():
     ps = api.params_struct(w.params)
     stream = torch.cuda.current_stream(dev).cuda_stream
 
-    def run(prec: str, steps: int, warmup: int, stage_steps: int):
+    def run(prec: str, steps: int, warmup: int, stage_steps: int, per_step: dict | None = None):
         """Time `steps` calls of hawkes_grad (the product path: the fix-up and
-        finalize chain overlaps pass 2 on a side stream), then take the
-        per-stage breakdown from `stage_steps` calls of hawkes_grad_timed,
-        which runs every stage in sequence on the one stream."""
+        finalize chain overlaps pass 2 on a side stream), bracketed by device
+        synchronizations, with a pair of HIP events on the call's stream
+        around every call (per_step receives their median, quartiles and
+        mean); then take the per-stage breakdown from `stage_steps` calls of
+        hawkes_grad_timed, which runs every stage in sequence on the one
+        stream with HIP events around each kernel."""
         pc = api._prec(prec)
         ws = api.workspace(n, d, prec, dev)
         ll = ctypes.c_double()
@@ -144,12 +152,22 @@ def main():
 
         for _ in range(warmup):
             call()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for a, b in evs:
+            a.record()
             call()
+            b.record()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        if per_step is not None:
+            ms = np.array([a.elapsed_time(b) for a, b in evs])
+            q1, med, q3 = np.percentile(ms, [25, 50, 75])
+            per_step.update({"median_ms": float(med), "iqr_ms": float(q3 - q1), "q1_ms": float(q1),
+                             "q3_ms": float(q3), "mean_ms": float(ms.mean()), "min_ms": float(ms.min()),
+                             "max_ms": float(ms.max()), "steps": int(steps),
+                             "note": "HIP events on the call's stream around each hawkes_grad call"})
         acc = np.zeros(len(STAGES))
         for _ in range(stage_steps if "+cull" not in prec else 0):
             st = L.hawkes_grad_timed(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), pc, ws.data_ptr(),
@@ -158,14 +176,16 @@ def main():
             acc += np.array(stage[:])
         return el / steps, acc / max(stage_steps, 1), ll.value
 
-    sec_mixed, stage_ms, ll_m = run(args.prec, args.steps, args.warmup, max(5, args.steps // 2))
+    step_stats = {}
+    sec_mixed, stage_ms, ll_m = run(args.prec, args.steps, args.warmup, max(5, args.steps // 2), step_stats)
     pairs = n * (n - 1)
     value = pairs / sec_mixed
 
     fp64 = None
     if args.prec == "mixed" and args.fp64_steps > 0:
-        sec64, stage64, ll_64 = run("fp64", args.fp64_steps, 1, 2)
-        fp64 = {"value": pairs / sec64, "ms_per_step": sec64 * 1e3,
+        st64 = {}
+        sec64, stage64, ll_64 = run("fp64", args.fp64_steps, 3, 2, st64)
+        fp64 = {"value": pairs / sec64, "ms_per_step": sec64 * 1e3, "per_step": st64,
                 "stage_ms": {k: round(float(v), 4) for k, v in zip(STAGES, stage64)},
                 "loglik_rel_diff_mixed_vs_fp64": abs(ll_m - ll_64) / abs(ll_64)}
 
@@ -188,23 +208,27 @@ def main():
                              "bitwise_equal": bool(ll_c == ll_ref and torch.equal(gx, ref))}
         gx.copy_(gx_all)
 
-    # dominant kernel and its roofline (algorithmic work per launch / measured duration)
+    # dominant kernel and its roofline (algorithmic work per launch / measured
+    # duration, the launch timed with HIP events on its own stream)
     pass_ms = {k: float(stage_ms[STAGES.index(k)]) for k in ("pass1", "pass2")}
     dom = max(pass_ms, key=pass_ms.get)
-    flops, exps = pass_work(d, dom, args.prec)
+    flops, exps = pass_work(d, dom)
     pairs_u = n * (n - 1) / 2
     work = pairs_u * (flops + exps * FLOP_EQ_PER_EXP)
     achieved = work / (pass_ms[dom] * 1e-3)
     peak = PEAK_FP32 if args.prec == "mixed" else PEAK_FP64
+    rf, re_ = pass_work_resplit(d, dom)
     roof = {"bound": "alu", "kernel": f"{KERNEL_NAMES[dom]}<D={d},{args.prec}>",
             "achieved": round(achieved / 1e12, 3), "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
             "traffic": measured_traffic(PROFILED_NAMES.get((dom, args.prec), "?"), w.name) if d == 2 else None,
             "work_per_unordered_pair": {"flops": flops, "exps": exps, "flop_eq_per_exp": FLOP_EQ_PER_EXP},
-            "kernel_ms": round(pass_ms[dom], 4)}
+            "units_per_launch": pairs_u, "kernel_ms": round(pass_ms[dom], 4),
+            "frac_at_resplit_count": round(pairs_u * (rf + re_ * FLOP_EQ_PER_EXP) / (pass_ms[dom] * 1e-3) / peak, 4),
+            "resplit_work_per_unordered_pair": {"flops": rf, "exps": re_}}
     # whole-path roofline: both passes' algorithmic work over the full step time
-    f1, e1 = pass_work(d, "pass1", args.prec)
-    f2, e2 = pass_work(d, "pass2", args.prec)
+    f1, e1 = pass_work(d, "pass1")
+    f2, e2 = pass_work(d, "pass2")
     path_work = pairs_u * (f1 + f2 + (e1 + e2) * FLOP_EQ_PER_EXP)
 
     mwg = mwg_bench(w, dev, args.mwg_steps) if args.mwg_steps > 0 else None
@@ -232,6 +256,9 @@ def main():
                       "pairs_per_step": pairs, "parallelism": "single-gpu"},
            "roofline": roof,
            "path_roofline_frac": round(path_work / sec_mixed / peak, 4),
+           "path_roofline_note": "both passes' algorithmic work (10D+39 FLOPs + 4 exps per unordered pair) over "
+                                 "ms_per_step, against the same peak",
+           "per_step": step_stats,
            "stage_ms": {k: round(float(v), 4) for k, v in zip(STAGES, stage_ms)},
            "stage_ms_note": "stages timed in sequence on one stream (hawkes_grad_timed); ms_per_step is "
                             "hawkes_grad, where fix1, final1 and fix2 overlap pass2 on a side stream",
@@ -448,22 +475,49 @@ def serving(n_requests: int, rate: float):
     return out
 
 
+def _cpu_model() -> str:
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, seconds: float):
-    """The oracle as it stands (OpenMP build over rows, all host cores) on the
-    first N_s events of the same workload, N_s sized for about `seconds`."""
+    """The oracle as it stands, on the first N_s events of the same workload
+    (N_s sized for about `seconds` of single-core work): its single-threaded
+    build on one core and its OpenMP build (rows split over threads; the same
+    arithmetic per row) on every core of the host, both on that same sample,
+    each the median of 3 runs.  value = the all-core rate."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    n0 = 2000
+    n0 = 1500
     t0 = time.perf_counter()
-    oracle.loglik_grad(w.x[:n0], w.t[:n0], w.params, threads=True)
+    oracle.loglik_grad(w.x[:n0], w.t[:n0], w.params, threads=False)
     dt0 = time.perf_counter() - t0
     ns = int(min(w.n, max(n0, n0 * (seconds / max(dt0, 1e-3)) ** 0.5)))
+    x, t = w.x[:ns], w.t[:ns]
+    one = []
     t0 = time.perf_counter()
-    st, ll, _, _ = oracle.loglik_grad(w.x[:ns], w.t[:ns], w.params, threads=True)
-    el = time.perf_counter() - t0
-    return {"value": ns * (ns - 1) / el, "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle loglik+grad (C, OpenMP rows) on the first {ns} of {w.n} events of {w.name}",
-            "seconds": round(el, 3)}
+    st, ll1, _, _ = oracle.loglik_grad(x, t, w.params, threads=False)
+    one.append(time.perf_counter() - t0)
+    allc = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        st, ll2, _, _ = oracle.loglik_grad(x, t, w.params, threads=True)
+        allc.append(time.perf_counter() - t0)
+    el1, elm = float(np.median(one)), float(np.median(allc))
+    return {"value": ns * (ns - 1) / elm, "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle loglik+grad (C, float64) on the first {ns} of {w.n} events of {w.name}",
+            "seconds": round(elm, 3),
+            "single_core": {"value": ns * (ns - 1) / el1, "cores": 1, "seconds": round(el1, 3),
+                            "build": "single-threaded oracle"},
+            "all_cores_build": "OpenMP over rows", "same_result": bool(ll1 == ll2),
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
 
 
 if __name__ == "__main__":

@@ -59,6 +59,7 @@ bool make_layout(int64_t n, int d, int prec, Layout& Lo) {
     Lo.items += (int)((nt + Lo.L - 1) / Lo.L);
   }
   Lo.nblk = (int)((n + kEvBlock - 1) / kEvBlock);
+  Lo.nsblk = (int)((n + kRedEv - 1) / kRedEv);
   const size_t real = Lo.mixed ? 4 : 8;
   const int rw = Lo.mixed ? ((d + 2 + 3) / 4) * 4 : ((d + 2 + 1) / 2) * 2;
   size_t o = 0;
@@ -80,8 +81,8 @@ bool make_layout(int64_t n, int d, int prec, Layout& Lo) {
   Lo.off_flags = take(sizeof(int) * (size_t)n);
   Lo.off_list = take(sizeof(int) * (size_t)n);
   Lo.off_listpos = take(sizeof(int) * (size_t)n);
-  Lo.off_bcount = take(sizeof(int) * (size_t)Lo.nblk);
-  Lo.off_bstage = take(sizeof(int) * (size_t)Lo.nblk * kEvBlock);
+  Lo.off_bcount = take(sizeof(int) * (size_t)Lo.nsblk);
+  Lo.off_bstage = take(sizeof(int) * (size_t)Lo.nsblk * kRedEv);
   Lo.off_logl = take(sizeof(double) * (size_t)n);
   Lo.off_bpart = take(sizeof(double) * 8 * (size_t)Lo.nblk);
   Lo.off_gfix = take(sizeof(double) * (size_t)d * n);
@@ -129,6 +130,7 @@ KParams make_kparams(const Layout& Lo, const hawkes_params_t* p) {
   k.items = Lo.items;
   k.d = D;
   k.nblk = Lo.nblk;
+  k.nsblk = Lo.nsblk;
   k.mu0 = p->mu;
   k.tau_x = p->h;
   k.tau_t = p->tau;
@@ -311,7 +313,7 @@ static bool launch_phases(const ReqDesc* reqs, int nreq, const BatchGrid& g, boo
     k_pass1<D, MIX><<<g.items, kThreads, 0, s>>>(reqs, nreq);
   }
   mark(s, 3);
-  k_reduce1<D, MIX><<<g.ev_blocks, kRedThreads, 0, s>>>(reqs, nreq);
+  k_reduce1<D, MIX><<<g.red_blocks, kRedThreads, 0, s>>>(reqs, nreq);
   mark(s, 4);
   const bool fork = grad && fk != nullptr;
   hipStream_t a = s;   // stream of the fix-up and finalize chain
@@ -342,7 +344,7 @@ static bool launch_phases(const ReqDesc* reqs, int nreq, const BatchGrid& g, boo
   if (fork) ok = ok && hipStreamWaitEvent(s, fk->done, 0) == hipSuccess;
   else k_fix2<D><<<fix2_blocks, kEvBlock, 0, s>>>(reqs, nreq, g.ev_blocks);
   mark(s, 8);
-  k_reduce2<D, MIX><<<g.ev_blocks, kRedThreads, 0, s>>>(reqs, nreq);
+  k_reduce2<D, MIX><<<g.red_blocks, kRedThreads, 0, s>>>(reqs, nreq);
   mark(s, 9);
   return ok;
 }
@@ -386,14 +388,16 @@ int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const Batc
 
 // Fill the block offsets of descriptors [0, nreq) and return the grid sizes.
 BatchGrid assign_blocks(ReqDesc* descs, int nreq) {
-  BatchGrid g{0, 0, 0};
+  BatchGrid g{0, 0, 0, 0};
   for (int r = 0; r < nreq; ++r) {
     descs[r].blk_items = g.items;
     descs[r].blk_ev = g.ev_blocks;
     descs[r].blk_pad = g.pad_blocks;
+    descs[r].blk_red = g.red_blocks;
     g.items += descs[r].kp.items;
     g.ev_blocks += descs[r].kp.nblk;
     g.pad_blocks += descs[r].kp.n_pad / kEvBlock;
+    g.red_blocks += descs[r].kp.nsblk;
   }
   return g;
 }

@@ -42,6 +42,8 @@ constexpr int kMaxD = 8;
 constexpr int kFixGrid = 256;            // workgroups per request in the fix-up kernels
 constexpr int kFixSeg = 16;             // partner segments per flagged row in the fix-up kernels
 constexpr int kEvBlock = 256;           // events per block of the per-event kernels
+constexpr int kRedEv = 64;              // events per workgroup of the partial-sum reductions
+constexpr int kRedWaves = 16;           // waves per reduction workgroup (each sums a stride of partials)
 // float32 pair passes: steps whose exps are issued together (rate, gradient)
 // Waves per SIMD the mixed passes are compiled for: the register budget
 // (512 / waves per lane) must hold the rows' state, which grows with D, or
@@ -90,6 +92,7 @@ struct KParams {
   int items;      // work items of a pair pass
   int d;
   int nblk;       // ceil(n / kEvBlock)
+  int nsblk;      // ceil(n / kRedEv): reduction workgroups (flagged-row staging blocks)
   int mixed;
   // model parameters (paper symbols)
   double mu0, tau_x, tau_t, theta, omega, h;
@@ -151,7 +154,7 @@ struct ReqDesc {
   int blk_items;    // first block of this request in a pair-pass launch
   int blk_ev;       // first block in a per-event launch (kEvBlock events per block)
   int blk_pad;      // first block in the pack launch (n_pad / kEvBlock blocks)
-  int pad_;
+  int blk_red;      // first block in a reduction launch (kRedEv events per block)
 };
 
 // Float64 exp of the pair passes and the Metropolis kernels, by Tang's table-driven method (P. T. P. Tang,

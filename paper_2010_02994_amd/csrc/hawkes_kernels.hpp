@@ -98,13 +98,16 @@ __device__ __forceinline__ double tile_origin(const double* t, int tile) {
 
 // Which request of a batched launch owns block `blk`: the last request whose
 // first block (offsets are non-decreasing) is <= blk.  kind 0: pair-pass
-// items, 1: per-event blocks, 2: pack blocks.
+// items, 1: per-event blocks, 2: pack blocks, 3: reduction blocks.
 __device__ __forceinline__ int find_req(const ReqDesc* __restrict__ reqs, int nreq, int blk, int kind) {
   if (nreq == 1) return 0;
   int lo = 0, hi = nreq - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int b = kind == 0 ? reqs[mid].blk_items : (kind == 1 ? reqs[mid].blk_ev : reqs[mid].blk_pad);
+    const int b = kind == 0 ? reqs[mid].blk_items
+                : kind == 1 ? reqs[mid].blk_ev
+                : kind == 2 ? reqs[mid].blk_pad
+                            : reqs[mid].blk_red;
     if (b <= blk) lo = mid; else hi = mid - 1;
   }
   return lo;
@@ -999,66 +1002,75 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(g
 // sums K, R, U, J, V, W (times exp(sigma)), the recompute flag, and the
 // pass-2 factors (1/lambda scaled to the main pass's terms; 0 for flagged rows,
 // whose pairs the float64 fix-ups take).  Pass 2 needs nothing later than this
-// kernel, so it can run while the fix-ups and the finalize kernels do.  Four lanes
-// share an event (each takes every fourth partial; the four partial sums are
-// combined by two butterfly steps, which gives every lane the same value; the
-// four lanes of an event always branch together), so the kernel keeps enough
-// loads in flight to stream the partial buffers.
-// Flagged rows of each block are staged in index order for k_fix1.
-constexpr int kRedThreads = 4 * kEvBlock;
-
-__device__ __forceinline__ double quad_sum(double v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  return v;
-}
+// kernel, so it can run while the fix-ups and the finalize kernels do.
+//
+// A workgroup takes kRedEv consecutive events (one band, since kRedEv divides
+// kBandRows), one per lane, in each of kRedWaves waves: wave w sums the items
+// c = w, w + kRedWaves, ... and the bands I = b + w, b + w + kRedWaves, ..., so
+// every load instruction reads one contiguous row of kRedEv float64 partials;
+// the waves' sums meet in LDS and wave 0 adds them in wave order (a fixed
+// order: results do not depend on timing).  Flagged rows of each workgroup are
+// staged in index order for k_fix1.
+constexpr int kRedThreads = 64 * kRedWaves;
+static_assert(kRedEv == 64 && kBandRows % kRedEv == 0, "a reduction workgroup is one wave of events inside one band");
 
 template <int D, bool MIX>
 __global__ void __launch_bounds__(kRedThreads) k_reduce1(const ReqDesc* __restrict__ reqs, int nreq) {
   using ColT = double;   // partials are float64 in both precisions
   using Real = typename Traits<D, MIX>::Real;
   using Rec = typename Traits<D, MIX>::Rec;
-  __shared__ int s_cnt[kRedThreads / 64];
-  const int rid = find_req(reqs, nreq, blockIdx.x, 1);
+  __shared__ double s_part[kRedWaves][6][kRedEv];
+  const int rid = find_req(reqs, nreq, blockIdx.x, 3);
   const ReqDesc& rq = reqs[rid];
   if (uni(glb(rq.status)[kStData]) != 0) return;
   const KParams& kp = rq.kp;
-  const int lb = blockIdx.x - rq.blk_ev;
-  const int sub = threadIdx.x & 3;
-  const int i = lb * kEvBlock + (threadIdx.x >> 2);
+  const int lb = blockIdx.x - rq.blk_red;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i0 = lb * kRedEv;
+  const int i = i0 + lane;   // >= n only in the last band's padding (read, never written)
+  const int b = i0 / kBandRows, lr = i % kBandRows;
+  const IPair bi{glb(rq.band)[b].x, glb(rq.band)[b].y};
+  const auto prow = glb(static_cast<const ColT*>(rq.prow));
+  const auto pcol = glb(static_cast<const ColT*>(rq.pcol));
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  if (!MIX || kp.ru1) {
+#pragma unroll 2
+    for (int c = wave; c < bi.y; c += kRedWaves) {
+      const auto p = prow + (int64_t)(bi.x + c) * 6 * kBandRows + lr;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) s[q] += p[(int64_t)q * kBandRows];
+    }
+#pragma unroll 2
+    for (int I = b + wave; I < kp.nb; I += kRedWaves) {
+      const auto p = pcol + (int64_t)I * 3 * kp.n_pad + i;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) s[q] += p[(int64_t)q * kp.n_pad];
+    }
+  } else {
+    // rate pass without the background moments: rows K, J, V, W, column K
+#pragma unroll 2
+    for (int c = wave; c < bi.y; c += kRedWaves) {
+      const auto p = prow + (int64_t)(bi.x + c) * 4 * kBandRows + lr;
+      s[0] += p[0];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) s[q + 2] += p[(int64_t)q * kBandRows];
+    }
+#pragma unroll 4
+    for (int I = b + wave; I < kp.nb; I += kRedWaves) s[0] += pcol[(int64_t)I * kp.n_pad + i];
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) s_part[wave][q][lane] = s[q];
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    double v = s_part[0][q][lane];
+#pragma unroll
+    for (int w = 1; w < kRedWaves; ++w) v += s_part[w][q][lane];
+    s[q] = v;
+  }
   bool flag = false;
   if (i < kp.n) {
-    const int b = i / kBandRows, lr = i % kBandRows;
-    const IPair bi{glb(rq.band)[b].x, glb(rq.band)[b].y};
-    double s[6] = {0, 0, 0, 0, 0, 0};
-    const auto pcol = glb(static_cast<const ColT*>(rq.pcol));
-    if (!MIX || kp.ru1) {
-#pragma unroll 4
-      for (int c = sub; c < bi.y; c += 4) {
-        const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * 6 * kBandRows + lr;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) s[q] += (double)p[(int64_t)q * kBandRows];
-      }
-#pragma unroll 4
-      for (int I = b + sub; I < kp.nb; I += 4) {
-        const auto p = pcol + (int64_t)I * 3 * kp.n_pad + i;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) s[q] += (double)p[(int64_t)q * kp.n_pad];
-      }
-    } else {
-      // rate pass without the background moments: rows K, J, V, W, column K
-#pragma unroll 4
-      for (int c = sub; c < bi.y; c += 4) {
-        const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * 4 * kBandRows + lr;
-        s[0] += (double)p[0];
-#pragma unroll
-        for (int q = 1; q < 4; ++q) s[q + 2] += (double)p[(int64_t)q * kBandRows];
-      }
-#pragma unroll 4
-      for (int I = b + sub; I < kp.nb; I += 4) s[0] += (double)pcol[(int64_t)I * kp.n_pad + i];
-    }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) s[q] = quad_sum(s[q]);
     if (MIX) {   // moments were accumulated in bandwidth units
       s[1] *= kp.tau_x * kp.tau_x;
       s[2] *= kp.tau_t * kp.tau_t;
@@ -1066,37 +1078,22 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce1(const ReqDesc* __restri
       s[5] *= kp.tau_t;
     }
     const double lam = kp.cbg * s[0] + kp.cse * s[3];
-    const bool fl = !(lam >= kp.cmax * exp2(kp.flag_floor));
-    flag = sub == 0 && fl;
-    if (sub == 0) {
+    flag = !(lam >= kp.cmax * exp2(kp.flag_floor));
 #pragma unroll
-      for (int q = 0; q < 6; ++q) glb(rq.sums)[(int64_t)i * 6 + q] = s[q];
-      glb(rq.sigma)[i] = kp.sigma_main;
-      glb(rq.flags)[i] = fl ? 1 : 0;
-      // mixed: coordinates are in units of tau_x, so one factor tau_x moves in
-      const double il = fl ? 0.0 : 1.0 / lam;
-      const double pb = MIX ? kp.cbg * kp.inv_tx * il : kp.cbg * kp.itx2 * il;
-      const double ps = MIX ? kp.cse * kp.tau_x * kp.ih2 * il : kp.cse * kp.ih2 * il;
-      glb(static_cast<Rec*>(rq.rec))[i].v[D + 1] = (Real)pb;
-      glb(static_cast<Real*>(rq.ps))[i] = (Real)ps;
-    }
+    for (int q = 0; q < 6; ++q) glb(rq.sums)[(int64_t)i * 6 + q] = s[q];
+    glb(rq.sigma)[i] = kp.sigma_main;
+    glb(rq.flags)[i] = flag ? 1 : 0;
+    // mixed: coordinates are in units of tau_x, so one factor tau_x moves in
+    const double il = flag ? 0.0 : 1.0 / lam;
+    const double pb = MIX ? kp.cbg * kp.inv_tx * il : kp.cbg * kp.itx2 * il;
+    const double ps = MIX ? kp.cse * kp.tau_x * kp.ih2 * il : kp.cse * kp.ih2 * il;
+    glb(static_cast<Rec*>(rq.rec))[i].v[D + 1] = (Real)pb;
+    glb(static_cast<Real*>(rq.ps))[i] = (Real)ps;
   }
-  // stage this block's flagged rows in index order (wave ballots, then waves in order)
+  // stage this workgroup's flagged rows in index order (one wave ballot)
   const unsigned long long m = __ballot(flag);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) s_cnt[w] = __popcll(m);
-  __syncthreads();
-  int before = 0;
-  for (int ww = 0; ww < w; ++ww) before += s_cnt[ww];
-  if (flag) {
-    const int pos = before + __popcll(m & ((1ull << lane) - 1ull));
-    glb(rq.bstage)[(int64_t)lb * kEvBlock + pos] = i;
-  }
-  if (threadIdx.x == 0) {
-    int tot = 0;
-    for (int ww = 0; ww < kRedThreads / 64; ++ww) tot += s_cnt[ww];
-    glb(rq.bcount)[lb] = tot;
-  }
+  if (flag) glb(rq.bstage)[(int64_t)lb * kRedEv + __popcll(m & ((1ull << lane) - 1ull))] = i;
+  if (lane == 0) glb(rq.bcount)[lb] = __popcll(m);
 }
 
 // Exact float64 recomputation of the six row sums of each flagged row.  The
@@ -1117,8 +1114,8 @@ __global__ void __launch_bounds__(256) k_fix1(const ReqDesc* __restrict__ reqs) 
   if (uni(glb(rq.status)[kStData]) != 0) return;
   const KParams& kp = rq.kp;
   const int tid = threadIdx.x;
-  const int per = (kp.nblk + 255) / 256;
-  const int lo = min(kp.nblk, tid * per), hi = min(kp.nblk, lo + per);
+  const int per = (kp.nsblk + 255) / 256;
+  const int lo = min(kp.nsblk, tid * per), hi = min(kp.nsblk, lo + per);
   int own = 0;
   for (int b = lo; b < hi; ++b) own += glb(rq.bcount)[b];
   s_scan[tid] = own;
@@ -1135,7 +1132,7 @@ __global__ void __launch_bounds__(256) k_fix1(const ReqDesc* __restrict__ reqs) 
     for (int b = lo; b < hi; ++b) {
       const int c = glb(rq.bcount)[b];
       for (int k = 0; k < c; ++k) {
-        const int i = glb(rq.bstage)[(int64_t)b * kEvBlock + k];
+        const int i = glb(rq.bstage)[(int64_t)b * kRedEv + k];
         glb(rq.list)[pos] = i;
         glb(rq.listpos)[i] = pos;
         ++pos;
@@ -1158,7 +1155,7 @@ __global__ void __launch_bounds__(256) k_fix1(const ReqDesc* __restrict__ reqs) 
     int r = f - (c0 > 0 ? s_scan[c0 - 1] : 0);
     int b = c0 * per;
     for (int cb = glb(rq.bcount)[b]; r >= cb; cb = glb(rq.bcount)[b]) { r -= cb; ++b; }
-    const int i = glb(rq.bstage)[(int64_t)b * kEvBlock + r];
+    const int i = glb(rq.bstage)[(int64_t)b * kRedEv + r];
     const int j0 = sg * seg, j1 = min(kp.n, j0 + seg);
     double xi[D];
 #pragma unroll
@@ -1407,18 +1404,17 @@ __global__ void __launch_bounds__(kEvBlock) k_fix2(const ReqDesc* __restrict__ r
   fix2a_block<D>(reqs[b / kFixGrid], b % kFixGrid, kFixGrid, sh);
 }
 
-// grad_x = row partials + column partials + fix-up terms (fixed order; four
-// lanes per event as in k_reduce1).
+// grad_x = row partials + column partials + fix-up terms, in a fixed order
+// (workgroups, waves and the LDS meeting as in k_reduce1).
 template <int D, bool MIX>
 __global__ void __launch_bounds__(kRedThreads) k_reduce2(const ReqDesc* __restrict__ reqs, int nreq) {
   using ColT = double;   // partials are float64 in both precisions
-  const int rid = find_req(reqs, nreq, blockIdx.x, 1);
+  __shared__ double s_part[kRedWaves][D][kRedEv];
+  const int rid = find_req(reqs, nreq, blockIdx.x, 3);
   const ReqDesc& rq = reqs[rid];
   const KParams& kp = rq.kp;
-  const int sub = threadIdx.x & 3;
-  const int i = (blockIdx.x - rq.blk_ev) * kEvBlock + (threadIdx.x >> 2);
   if (uni(glb(rq.status)[kStData]) != 0) return;
-  if (MIX && !kp.ru1 && (int)blockIdx.x == rq.blk_ev) {
+  if (MIX && !kp.ru1 && (int)blockIdx.x == rq.blk_red) {
     // the background moments' terms of d ell/d tau_x and d ell/d tau_t, from
     // the gradient pass's item sums in item order: sum over pairs of
     // w r'^2 = sum_n c_bg R_n / (tau_x^3 lambda_n) and w dt'^2 tau_x / tau_t =
@@ -1452,36 +1448,46 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce2(const ReqDesc* __restri
   }
   if (rq.grad_x == nullptr) return;
   const auto grad_x = glb(rq.grad_x);
+  const int lb = blockIdx.x - rq.blk_red;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i0 = lb * kRedEv;
+  const int i = i0 + lane;   // >= n only in the last band's padding (read, never written)
   if (uni(glb(rq.status)[kStZero]) != 0) {
-    if (i < kp.n && sub == 0)
+    if (wave == 0 && i < kp.n)
 #pragma unroll
       for (int q = 0; q < D; ++q) grad_x[(int64_t)i * D + q] = NAN;
     return;
   }
-  if (i >= kp.n) return;   // the four lanes of an event leave together
+  const int b = i0 / kBandRows, lr = i % kBandRows;
+  const IPair bi{glb(rq.band)[b].x, glb(rq.band)[b].y};
+  const auto prow = glb(static_cast<const ColT*>(rq.prow));
+  const auto pcol = glb(static_cast<const ColT*>(rq.pcol));
   double s[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) s[q] = 0.0;
-  const int b = i / kBandRows, lr = i % kBandRows;
-  const IPair bi{glb(rq.band)[b].x, glb(rq.band)[b].y};
-#pragma unroll 4
-  for (int c = sub; c < bi.y; c += 4) {
-    const auto p = glb(static_cast<const ColT*>(rq.prow)) + (int64_t)(bi.x + c) * D * kBandRows + lr;
+#pragma unroll 2
+  for (int c = wave; c < bi.y; c += kRedWaves) {
+    const auto p = prow + (int64_t)(bi.x + c) * D * kBandRows + lr;
 #pragma unroll
-    for (int q = 0; q < D; ++q) s[q] += (double)p[(int64_t)q * kBandRows];
+    for (int q = 0; q < D; ++q) s[q] += p[(int64_t)q * kBandRows];
   }
-  const auto pcol = glb(static_cast<const ColT*>(rq.pcol));
-#pragma unroll 4
-  for (int I = b + sub; I < kp.nb; I += 4) {
+#pragma unroll 2
+  for (int I = b + wave; I < kp.nb; I += kRedWaves) {
     const auto p = pcol + (int64_t)I * D * kp.n_pad + i;
 #pragma unroll
-    for (int q = 0; q < D; ++q) s[q] += (double)p[(int64_t)q * kp.n_pad];
+    for (int q = 0; q < D; ++q) s[q] += p[(int64_t)q * kp.n_pad];
   }
 #pragma unroll
-  for (int q = 0; q < D; ++q) s[q] = quad_sum(s[q]);
-  if (sub != 0) return;
+  for (int q = 0; q < D; ++q) s_part[wave][q][lane] = s[q];
+  __syncthreads();
+  if (wave != 0 || i >= kp.n) return;
 #pragma unroll
-  for (int q = 0; q < D; ++q) s[q] += glb(rq.gfix)[(int64_t)i * D + q];
+  for (int q = 0; q < D; ++q) {
+    double v = s_part[0][q][lane];
+#pragma unroll
+    for (int w = 1; w < kRedWaves; ++w) v += s_part[w][q][lane];
+    s[q] = v + glb(rq.gfix)[(int64_t)i * D + q];
+  }
   if (glb(rq.flags)[i] != 0) {
     const auto fp = glb(rq.fixpart) + (int64_t)glb(rq.listpos)[i] * kFixSeg * 8;
     for (int g = 0; g < kFixSeg; ++g)
