@@ -95,8 +95,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="single-core oracle seconds the CPU baseline's sample is sized for")
-    ap.add_argument("--serve-requests", type=int, default=2000,
-                    help="requests per precision in the serving run (0 skips it)")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests measured per precision in the long serving run (0 skips serving)")
+    ap.add_argument("--serve-sweep-requests", type=int, default=1500,
+                    help="requests per offered rate in the serving saturation sweep (0 skips the sweep)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--cull-steps", type=int, default=5,
                     help="timed steps with exact culling, reported apart from the headline (0 skips)")
@@ -242,7 +244,7 @@ def main():
 
     serve = None
     if args.serve_requests > 0:
-        serve = serving(args.serve_requests, args.serve_rate)
+        serve = serving(args.serve_requests, args.serve_rate, args.serve_sweep_requests)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -461,16 +463,36 @@ def bmds_bench(dev, reps: int):
     return out
 
 
-def serving(n_requests: int, rate: float):
+def serving(n_requests: int, rate: float, sweep_requests: int):
     """64 HMC chains over 64 datasets with N log-uniform in [1e3, 1e5] (D = 2,
-    coarsened to a 100 m grid), open-loop Poisson arrivals; mixed, then FP64."""
+    coarsened to a 100 m grid), open-loop Poisson arrivals.  For each precision:
+    the long run (n_requests measured after a 5 s warm-up at `rate`), then an
+    offered-rate sweep up to and beyond saturation (sweep_requests each, 1 s
+    warm-up), whose highest achieved throughput is the measured capacity."""
     from paper_2010_02994_amd import loadgen
     from paper_2010_02994_amd.serve import Server
-    out = {"chains": 64, "n_range": [1000, 100000], "offered_rate_req_s": rate}
+    out = {"chains": 64, "n_range": [1000, 100000], "offered_rate_req_s": rate, "streams": 3, "max_slots": 64,
+           "hbm_budget_GiB": 24}
+    sweeps = {"mixed": [400.0, 800.0, 1600.0, 3200.0], "fp64": [300.0, 600.0, 1200.0]}
     with Server(hbm_budget_bytes=24 << 30, max_slots=64, streams=3) as srv:
         chains = loadgen.Chains(srv, count=64)
         for prec in ("mixed", "fp64"):
-            out[prec] = loadgen.run(srv, chains, rate=rate, n_requests=n_requests, prec=prec, warmup=100)
+            out[prec] = loadgen.run(srv, chains, rate=rate, n_requests=n_requests, prec=prec, warmup_s=5.0)
+            print(f"serve {prec} at {rate:.0f} req/s: p50 {out[prec]['p50_ms']:.2f} ms, "
+                  f"p99 {out[prec]['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+            sw = []
+            for r in sweeps[prec] if sweep_requests > 0 else []:
+                res = loadgen.run(srv, chains, rate=r, n_requests=sweep_requests, prec=prec, warmup_s=1.0)
+                sw.append({k: res[k] for k in ("offered_rate", "submit_rate_req_s", "throughput_req_s", "pairs_per_s",
+                                               "p50_ms", "p99_ms", "queue_wait_ms", "admit_to_start_ms",
+                                               "service_ms", "requests", "errors", "unfinished")})
+                print(f"serve {prec} sweep {r:.0f} req/s: {res['throughput_req_s']:.0f} req/s, "
+                      f"p50 {res['p50_ms']:.1f} ms", file=sys.stderr, flush=True)
+            out[prec + "_sweep"] = sw
+            if sw:
+                best = max(sw, key=lambda e: e["throughput_req_s"] or 0.0)
+                out[prec + "_capacity_req_s"] = best["throughput_req_s"]
+                out[prec + "_capacity_pairs_per_s"] = best["pairs_per_s"]
         out["batches_launched"] = srv.stats()["batches_launched"]
     return out
 

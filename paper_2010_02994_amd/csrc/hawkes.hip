@@ -21,7 +21,7 @@ namespace hawkes {
 constexpr double kShiftMixed = 120.0;       // base-2 shift of the mixed pass's terms
 constexpr double kFloorMixed = -60.0;       // flag when lambda * 2^S < cmax * 2^-60
 constexpr double kFloorFp64 = -900.0;       // flag when lambda < cmax * 2^-900
-constexpr int kTargetItems = 5120;
+constexpr int kTargetItems = 10240;   // about six rounds of the chip's concurrent pair-pass workgroups
 constexpr int kNumStages = 9;
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -34,8 +34,10 @@ static int tiles_per_item(int64_t n) {
   const int nb = (int)((n + kBandRows - 1) / kBandRows);
   int64_t tiles = 0;
   for (int b = 0; b < nb; ++b) tiles += (std::min<int64_t>(n, (int64_t)(b + 1) * kBandRows) + kTile - 1) / kTile;
-  // about kTargetItems work items for a full chip; at small N, where that
-  // would leave one tile per item, up to four tiles per item (fewer row
+  // about kTargetItems work items (several rounds of the chip's workgroups,
+  // so the last round's idle tail is a small share; at N = 50,000 four tiles
+  // per item measured fastest against 3, 5, 6, 8 and 16); at small N, where
+  // that would leave one tile per item, up to four tiles per item (fewer row
   // partials for the reductions to read; measured best at N = 4,000-10,000)
   const int64_t fill = (tiles + kTargetItems - 1) / kTargetItems;
   const int64_t small = std::min<int64_t>(4, (tiles + 159) / 160);

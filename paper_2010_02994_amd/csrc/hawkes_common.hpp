@@ -14,13 +14,13 @@ namespace hawkes {
 #define HK_ROWS_PER_LANE 2
 #endif
 #ifndef HK_RATE_WAVES_PER_EU
-#define HK_RATE_WAVES_PER_EU 5
+#define HK_RATE_WAVES_PER_EU 4
 #endif
 #ifndef HK_GRAD_WAVES_PER_EU
-#define HK_GRAD_WAVES_PER_EU 6
+#define HK_GRAD_WAVES_PER_EU 5
 #endif
 #ifndef HK_RATE_EXP_STEPS
-#define HK_RATE_EXP_STEPS 2
+#define HK_RATE_EXP_STEPS 1
 #endif
 #ifndef HK_GRAD_EXP_STEPS
 #define HK_GRAD_EXP_STEPS 1

@@ -132,7 +132,7 @@ def test_open_loop_short_run():
     with Server(hbm_budget_bytes=16 << 30, max_slots=64, streams=2) as s:
         say("case serve open loop")
         chains = loadgen.Chains(s, count=16, lo=1e3, hi=2e4)
-        out = loadgen.run(s, chains, rate=200.0, n_requests=200, prec="mixed", warmup=20)
+        out = loadgen.run(s, chains, rate=200.0, n_requests=200, prec="mixed", warmup_s=0.1)
     say(f"  open loop: {out}")
     assert out["requests"] == 200 and out["errors"] == 0 and out["unfinished"] == 0
     assert out["p50_ms"] > 0 and out["p99_ms"] >= out["p50_ms"]
