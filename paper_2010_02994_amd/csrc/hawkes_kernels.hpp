@@ -582,14 +582,14 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ 
 // constant offset.
 //
 // Float32 sums are micro-partials of at most 32 terms, folded into float64:
-// every kColSteps = 16 steps (16 steps x 2 rows = 32 terms) each lane adds
+// every kColSteps = 32 / kRowsPerLane steps (16 steps x 2 rows = 32 terms) each lane adds
 // its rotating column accumulator, converted to float64, to its column's slot
 // of the wave's float64 LDS row with an LDS add (lanes hold distinct columns
 // and a wave's LDS operations run in program order, so each slot receives its
 // four adds in a fixed order), and restarts it at zero; the row sums are
 // folded into their float64 accumulators every kRowFold = 32 steps.
 // Everything stored outside the wave is float64.
-constexpr int kColSteps = 16;
+constexpr int kColSteps = 32 / kRowsPerLane;
 constexpr int kRowFold = 32;
 static_assert(kColSteps * kRowsPerLane <= 32 && kRowFold <= 32 && kRowFold % kColSteps == 0 && 64 % kRowFold == 0,
               "float32 micro-partials hold at most 32 terms");
