@@ -107,6 +107,8 @@ def main():
                     help="timed Bayesian MDS evaluations per case and precision (0 skips)")
     ap.add_argument("--hmc-only", action="store_true",
                     help="run only the leapfrog measurement (for profiling its kernels on their own)")
+    ap.add_argument("--bmds-only", action="store_true",
+                    help="run only the Bayesian MDS measurement (for profiling its kernels on their own)")
     ap.add_argument("--hmc-trajectories", type=int, default=3,
                     help="timed 20-step device leapfrog trajectories on the gridded 10,000-event workload (0 skips)")
     ap.add_argument("--mwg-steps", type=int, default=3000,
@@ -122,6 +124,9 @@ def main():
     from paper_2010_02994_amd import _lib, api, workloads
 
     dev = torch.device("cuda:0")
+    if args.bmds_only:
+        print(json.dumps({"bmds": bmds_bench(dev, max(1, args.bmds_reps))}), flush=True)
+        return
     if args.hmc_only:
         print(json.dumps({"hmc": leapfrog_bench(dev, max(1, args.hmc_trajectories))}), flush=True)
         return
