@@ -444,7 +444,11 @@ def bmds_bench(dev, reps: int):
     (N = 4,733 cases in D = 6, 64 countries, dissimilarities between country
     centres, same-country pairs unobserved) and a larger N = 20,000, D = 6 case
     (|z_n - z_n'| plus folded normal noise), both drawn on the device.  The pass reads the strict lower triangle of the float64
-    matrix once, so its roofline is HBM: 4 N (N - 1) bytes per evaluation."""
+    matrix once, so its roofline is HBM: 4 N (N - 1) bytes per evaluation.  Beside it, the VALU roofline of the pair
+    arithmetic: per pair 7D + 8 FLOPs (differences D, squared distance 2D - 1, residual and its square 3, the log Phi
+    and rho z sums 3, the coefficient 3, gradient rows and columns 4D) and three special functions (the distance's
+    square root and reciprocal, the normal density's exponential, log Phi) at 8 FLOP-equivalents each, against the
+    float32 (157.3) or float64 (78.6 TFLOP/s) vector peak."""
     import torch
     from paper_2010_02994_amd import api, workloads
     out = {}
@@ -461,9 +465,13 @@ def bmds_bench(dev, reps: int):
                 o, gx = api.bmds(x, dl, sigma, prec=prec, grad_x=gx, out4=o)
             torch.cuda.synchronize()
             el = (time.perf_counter() - t0) / reps
+            flop_eq = 7 * x.shape[1] + 8 + 3 * 8
+            valu_tflops = 0.5 * n * (n - 1) * flop_eq / el / 1e12
             rec[prec] = {"ms": el * 1e3, "pair_interactions_per_s": n * (n - 1) / el,
                          "delta_GB_per_s": 4 * n * (n - 1) / el / 1e9,
-                         "hbm_frac": 4 * n * (n - 1) / el / 8e12, "status": float(o[3].item())}
+                         "hbm_frac": 4 * n * (n - 1) / el / 8e12, "status": float(o[3].item()),
+                         "valu_flop_eq_per_pair": flop_eq, "valu_tflops": valu_tflops,
+                         "valu_frac": valu_tflops / (157.3 if prec == "mixed" else 78.6)}
         out[name] = rec
         del x, dl
     return out

@@ -657,54 +657,56 @@ __global__ void __launch_bounds__(kFinalThreads) k_bmds_final(Args a) {
 }
 
 // Per event: its row partials over the chunks of its band, then its column
-// partials over the bands that reach its chunk.  Four lanes share an event
-// (each takes every fourth chunk and band, in order; two butterfly steps
-// combine the four sums in a fixed order, the same on every lane), so the
-// first events, whose columns collect a partial from nearly every band, do not
-// keep one long chain of loads each.
-constexpr int kRedEvents = 64;   // events per workgroup of k_bmds_reduce (256 lanes)
+// partials over the bands (tiles) or segments (strips) that reach its chunk.
+// A workgroup takes 64 consecutive events, which share one band and one chunk,
+// one event per lane, so each partial is read by a wave as one contiguous run;
+// its kRedWavesB waves take every kRedWavesB-th chunk and band or segment, in
+// order, and the waves' sums are added in wave order.
+constexpr int kRedWavesB = 16;
 
 template <int D, typename PT>
-__global__ void __launch_bounds__(4 * kRedEvents) k_bmds_reduce(Args a) {
+__global__ void __launch_bounds__(64 * kRedWavesB) k_bmds_reduce(Args a) {
+  __shared__ double s_part[kRedWavesB][D][64];
   const PT* prow = static_cast<const PT*>(a.prow);
   const PT* pcol = static_cast<const PT*>(a.pcol);
-  const int n = blockIdx.x * kRedEvents + (threadIdx.x >> 2);
-  const int sub = threadIdx.x & 3;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n0 = blockIdx.x * 64;   // a multiple of kTR: the band's first row
+  const int n = n0 + lane;
   const bool live = n < a.n;
   const bool bad = a.out4[3] != 0.0;
   double g[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) g[q] = 0.0;
   if (live && !bad) {
-    const int I = n / kTR, r = n % kTR;
+    const int I = n0 / kTR;
     const int64_t o = band_offset(I);
-    for (int J = sub; J <= I / 4; J += 4)
+    for (int J = w; J <= I / 4; J += kRedWavesB)
 #pragma unroll
-      for (int q = 0; q < D; ++q) g[q] += (double)prow[((o + J) * kTR + r) * D + q];
-    const int J = n / kTC, c = n % kTC;
+      for (int q = 0; q < D; ++q) g[q] += (double)prow[((o + J) * kTR + lane) * D + q];
+    const int J = n0 / kTC, c = n % kTC;
     if (a.seg_k > 0) {   // strips: the segments of chunk J
       const int64_t base = seg_base(J, a.seg_k, a.seg_m);
       const int cnt = a.seg_m - seg_m0(J, a.seg_k);
-      for (int sg = sub; sg < cnt; sg += 4)
+      for (int sg = w; sg < cnt; sg += kRedWavesB)
 #pragma unroll
         for (int q = 0; q < D; ++q) g[q] += (double)pcol[((base + sg) * kTC + c) * D + q];
     } else {
-      for (int Ib = 4 * J + sub; Ib < a.nb; Ib += 4)
+      for (int Ib = 4 * J + w; Ib < a.nb; Ib += kRedWavesB)
 #pragma unroll
         for (int q = 0; q < D; ++q) g[q] += (double)pcol[((band_offset(Ib) + J) * kTC + c) * D + q];
     }
   }
-  // the four lanes of an event are adjacent lanes of one wave, all present
+#pragma unroll
+  for (int q = 0; q < D; ++q) s_part[w][q][lane] = g[q];
+  __syncthreads();
+  if (w != 0 || !live) return;
 #pragma unroll
   for (int q = 0; q < D; ++q) {
-    g[q] += __shfl_xor(g[q], 1);
-    g[q] += __shfl_xor(g[q], 2);
-  }
-  if (!live || sub != 0) return;
+    double t = 0.0;
 #pragma unroll
-  for (int q = 0; q < D; ++q) {
+    for (int ww = 0; ww < kRedWavesB; ++ww) t += s_part[ww][q][lane];
     const int64_t e = (int64_t)n * D + q;
-    a.grad_x[e] = bad ? NAN : (a.accumulate ? a.grad_x[e] + g[q] : g[q]);
+    a.grad_x[e] = bad ? NAN : (a.accumulate ? a.grad_x[e] + t : t);
   }
 }
 
@@ -752,10 +754,10 @@ static void launch(const Args& a, int prec, hipStream_t s, int phase) {
     k_bmds_final<<<1, kFinalThreads, 0, s>>>(a);
   }
   if (phase != 1 && a.grad_x) {
-    const unsigned nred = (unsigned)((a.n + kRedEvents - 1) / kRedEvents);
+    const unsigned nred = (unsigned)((a.n + 63) / 64);
     // the strips store float32 partials for float32 pairs
-    if (a.seg_k > 0 && prec == HAWKES_MIXED) k_bmds_reduce<D, float><<<nred, 4 * kRedEvents, 0, s>>>(a);
-    else k_bmds_reduce<D, double><<<nred, 4 * kRedEvents, 0, s>>>(a);
+    if (a.seg_k > 0 && prec == HAWKES_MIXED) k_bmds_reduce<D, float><<<nred, 64 * kRedWavesB, 0, s>>>(a);
+    else k_bmds_reduce<D, double><<<nred, 64 * kRedWavesB, 0, s>>>(a);
   }
 }
 
