@@ -525,32 +525,36 @@ def _cpu_model() -> str:
 
 def cpu_baseline(w, seconds: float):
     """The oracle as it stands, on the first N_s events of the same workload
-    (N_s sized for about `seconds` of single-core work): its single-threaded
-    build on one core and its OpenMP build (rows split over threads; the same
-    arithmetic per row) on every core of the host, both on that same sample,
-    each the median of 3 runs.  value = the all-core rate."""
+    (N_s sized so that three single-core runs take about `seconds`): its
+    single-threaded build on one core and its OpenMP build (rows split over
+    threads; the same arithmetic per row) on every core of the host, both on
+    that same sample, three runs each (median and interquartile range of the
+    times).  value = the all-core rate at the median time."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     n0 = 1500
     t0 = time.perf_counter()
     oracle.loglik_grad(w.x[:n0], w.t[:n0], w.params, threads=False)
     dt0 = time.perf_counter() - t0
-    ns = int(min(w.n, max(n0, n0 * (seconds / max(dt0, 1e-3)) ** 0.5)))
+    ns = int(min(w.n, max(n0, n0 * (seconds / 3 / max(dt0, 1e-3)) ** 0.5)))
     x, t = w.x[:ns], w.t[:ns]
-    one = []
-    t0 = time.perf_counter()
-    st, ll1, _, _ = oracle.loglik_grad(x, t, w.params, threads=False)
-    one.append(time.perf_counter() - t0)
-    allc = []
-    for _ in range(3):
-        t0 = time.perf_counter()
-        st, ll2, _, _ = oracle.loglik_grad(x, t, w.params, threads=True)
-        allc.append(time.perf_counter() - t0)
-    el1, elm = float(np.median(one)), float(np.median(allc))
-    return {"value": ns * (ns - 1) / elm, "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
+
+    def runs(threaded):
+        el, ll = [], None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            st, ll, _, _ = oracle.loglik_grad(x, t, w.params, threads=threaded)
+            el.append(time.perf_counter() - t0)
+        q1, med, q3 = (float(v) for v in np.percentile(el, [25, 50, 75]))
+        return {"median_s": round(med, 4), "iqr_s": round(q3 - q1, 4), "runs_s": [round(v, 4) for v in el]}, ll
+
+    one, ll1 = runs(False)
+    allc, ll2 = runs(True)
+    pairs = ns * (ns - 1)
+    return {"value": pairs / allc["median_s"], "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
             "sample": f"oracle loglik+grad (C, float64) on the first {ns} of {w.n} events of {w.name}",
-            "seconds": round(elm, 3),
-            "single_core": {"value": ns * (ns - 1) / el1, "cores": 1, "seconds": round(el1, 3),
+            "seconds": allc["median_s"], "times": allc,
+            "single_core": {"value": pairs / one["median_s"], "cores": 1, "seconds": one["median_s"], "times": one,
                             "build": "single-threaded oracle"},
             "all_cores_build": "OpenMP over rows", "same_result": bool(ll1 == ll2),
             "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
