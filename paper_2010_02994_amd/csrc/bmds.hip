@@ -142,6 +142,24 @@ __device__ __forceinline__ double mills_s64(double u) {
   return __builtin_fma(p, u, 0.9999999999972508);
 }
 
+// 1/sqrt(r2) in float64 for r2 >= 0 (0 for r2 = 0: a coincident pair adds no
+// direction): the hardware reciprocal square root refined by two
+// Newton-Raphson steps, y <- y + y (1 - r2 y^2) / 2, each of which squares the
+// relative error, so the result is within a few units of the last place of
+// the correctly rounded value (the library square root and division cost
+// about twice the instructions).  Below 2^-1000 (and for infinities) the
+// library is used, away from the hardware estimate's denormal range.
+__device__ __forceinline__ double rsqrt_f64(double r2) {
+  if (__builtin_expect(r2 > 0x1p-1000 && r2 < 0x1p1000, 1)) {
+    double y = __builtin_amdgcn_rsq(r2);
+    double e = __builtin_fma(-r2 * y, y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    e = __builtin_fma(-r2 * y, y, 1.0);
+    return __builtin_fma(0.5 * y, e, y);
+  }
+  return r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
+}
+
 // log Phi(z) and rho/sigma = phi(z)/(sigma Phi(z)) of one observed pair at
 // distance dist = r2 rs (rs = 1/dist, 0 for a coincident pair); z = dist/sigma.
 // The upper tail is formed directly, so log Phi keeps small tails.  Beyond
@@ -289,8 +307,8 @@ __global__ void __launch_bounds__(TileShape<C>::kLanes) k_bmds_tiles(Args a) {
               rs = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;   // d = 0 adds no direction
               dist = r2 * rs;
             } else {
-              dist = sqrt(r2);
-              rs = dist > 0.0 ? 1.0 / dist : 0.0;
+              rs = rsqrt_f64(r2);
+              dist = r2 * rs;
             }
             R lphi, rho_s;
             pair_phi<R>(r2, dist, rs, a, s_exptab, lphi, rho_s);
@@ -472,8 +490,8 @@ __device__ __forceinline__ void strip_row(const Args& a, const double* __restric
           rs = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
           dist = r2 * rs;
         } else {
-          dist = sqrt(r2);
-          rs = dist > 0.0 ? 1.0 / dist : 0.0;
+          rs = rsqrt_f64(r2);
+          dist = r2 * rs;
         }
         R lphi, rho_s;
         pair_phi<R>(r2, dist, rs, a, tab, lphi, rho_s);
