@@ -236,6 +236,34 @@ def test_translation_offset_mixed_stable(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_long_work_items_dense_cluster(prec):
+    """Every tile of a band in one work item (HAWKES_TILES_PER_ITEM = 94 at
+    N = 6,000, items of up to 6,016 columns) on a dense cluster whose pair
+    terms all sit near their largest value (locations within ~1e-3 of the
+    spatial bandwidths, times within half the temporal one): each item's row
+    sums collect up to 6,000 near-maximal terms, which the float32
+    micro-partials (at most 32 terms) and the float64 accumulators must carry
+    without overflow."""
+    import os
+    w0 = W.random_case(41, 6000, 2, t_span=0.5)
+    params = np.array([0.5, 1.0, 1.0, 0.5, 1.0, 0.5])
+    x = np.ascontiguousarray(1e-3 * w0.x)
+    say(f"case long work items, dense cluster n=6000 L=94 prec={prec}")
+    ref = oracle_ref(x, w0.t, params)
+    old = os.environ.get("HAWKES_TILES_PER_ITEM")
+    os.environ["HAWKES_TILES_PER_ITEM"] = "94"
+    try:
+        got = run_gpu(x, w0.t, params, prec)
+    finally:
+        if old is None:
+            os.environ.pop("HAWKES_TILES_PER_ITEM", None)
+        else:
+            os.environ["HAWKES_TILES_PER_ITEM"] = old
+    assert np.isfinite(got[0])
+    check(prec, got, ref, params, label="dense_cluster_n6000_L94")
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_all_tied_is_zero_rate(prec):
     x = np.random.default_rng(1).standard_normal((70, 2))
     t = np.full(70, 1.5)
