@@ -26,6 +26,27 @@ constexpr int kNumStages = 9;
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// The pair passes dispatch bands from the last to the first, so the first
+// bands' items run last.  Split into one-tile items, they end the launch with
+// short workgroups, so the chip drains in about a tile's time instead of an
+// item's.  The split covers the first bands whose tiles total at most
+// kTailTiles (about one round of the chip's concurrent workgroups).
+#ifndef HK_TAIL_TILES
+#define HK_TAIL_TILES 1280
+#endif
+constexpr int64_t kTailTiles = HK_TAIL_TILES;
+static int fine_bands(int64_t n, int nb, int L) {
+  if (L <= 1) return 0;
+  int64_t tiles = 0;
+  int b = 0;
+  for (; b < nb; ++b) {
+    const int64_t nt = (std::min<int64_t>(n, (int64_t)(b + 1) * kBandRows) + kTile - 1) / kTile;
+    if (tiles + nt > kTailTiles) break;
+    tiles += nt;
+  }
+  return b;
+}
+
 static int tiles_per_item(int64_t n) {
   if (const char* e = std::getenv("HAWKES_TILES_PER_ITEM")) {
     const int v = std::atoi(e);
@@ -55,10 +76,12 @@ bool make_layout(int64_t n, int d, int prec, Layout& Lo) {
   Lo.nb = (int)((n + kBandRows - 1) / kBandRows);
   Lo.n_pad = Lo.nb * kBandRows;
   Lo.L = tiles_per_item(n);
+  Lo.b_fine = fine_bands(n, Lo.nb, Lo.L);
   Lo.items = 0;
   for (int b = 0; b < Lo.nb; ++b) {
     const int64_t nt = (std::min<int64_t>(n, (int64_t)(b + 1) * kBandRows) + kTile - 1) / kTile;
-    Lo.items += (int)((nt + Lo.L - 1) / Lo.L);
+    const int Lb = item_tiles(b, Lo.b_fine, Lo.L);
+    Lo.items += (int)((nt + Lb - 1) / Lb);
   }
   Lo.nblk = (int)((n + kEvBlock - 1) / kEvBlock);
   Lo.nsblk = (int)((n + kRedEv - 1) / kRedEv);
@@ -129,6 +152,7 @@ KParams make_kparams(const Layout& Lo, const hawkes_params_t* p) {
   k.n_pad = Lo.n_pad;
   k.nb = Lo.nb;
   k.L = Lo.L;
+  k.b_fine = Lo.b_fine;
   k.items = Lo.items;
   k.d = D;
   k.nblk = Lo.nblk;

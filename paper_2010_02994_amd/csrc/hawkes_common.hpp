@@ -51,6 +51,9 @@ constexpr int kRedWaves = 16;           // waves per reduction workgroup (each s
 // records take fewer waves.
 constexpr int rate_waves(int d, bool ru) { return ru && d >= 2 ? 4 : HK_RATE_WAVES_PER_EU; }
 constexpr int grad_waves(int d) { return d <= 2 ? HK_GRAD_WAVES_PER_EU : d <= 4 ? 5 : d <= 6 ? 4 : 3; }
+// Column tiles of a work item of band `band`.
+__host__ __device__ inline int item_tiles(int band, int b_fine, int L) { return band < b_fine ? 1 : L; }
+
 constexpr int kRateExpSteps = HK_RATE_EXP_STEPS;
 constexpr int kGradExpSteps = HK_GRAD_EXP_STEPS;
 
@@ -88,7 +91,8 @@ struct KParams {
   int n;          // events
   int n_pad;      // NB * kBandRows
   int nb;         // row bands
-  int L;          // column tiles per work item
+  int L;          // column tiles per work item (bands below b_fine: one)
+  int b_fine;     // bands dispatched last, split into one-tile items
   int items;      // work items of a pair pass
   int d;
   int nblk;       // ceil(n / kEvBlock)

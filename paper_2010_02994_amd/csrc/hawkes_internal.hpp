@@ -14,7 +14,7 @@ namespace hawkes {
 struct Layout {
   int64_t n = 0;
   int d = 0, mixed = 0, cull = 0;
-  int nb = 0, n_pad = 0, L = 1, items = 0, nblk = 0, nsblk = 0;
+  int nb = 0, n_pad = 0, L = 1, b_fine = 0, items = 0, nblk = 0, nsblk = 0;
   size_t off_desc, off_status, off_dconst, off_out8, off_items, off_band, off_rec, off_first, off_ps, off_prow,
       off_pcol, off_sums, off_sigma, off_flags, off_list, off_listpos, off_bcount, off_bstage, off_logl, off_bpart,
       off_gfix, off_fixpart, off_mompart, total;

@@ -125,7 +125,7 @@ template <int D>
 __device__ __forceinline__ void init_block(const ReqDesc& rq) {
   const auto x = glb(rq.x);
   const auto t = glb(rq.t);
-  const int n = rq.kp.n, nb = rq.kp.nb, L = rq.kp.L;
+  const int n = rq.kp.n, nb = rq.kp.nb, L = rq.kp.L, b_fine = rq.kp.b_fine;
   __shared__ int s_wsum[1024 / 64];
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -144,7 +144,8 @@ __device__ __forceinline__ void init_block(const ReqDesc& rq) {
       const int b = nb - 1 - pos;
       const int row_end = min(n, (b + 1) * kBandRows);
       const int nt = (row_end + kTile - 1) / kTile;
-      local += (nt + L - 1) / L;
+      const int Lb = item_tiles(b, b_fine, L);
+      local += (nt + Lb - 1) / Lb;
     }
   }
   // exclusive scan of the item counts: within each wave by shuffles, then
@@ -166,7 +167,8 @@ __device__ __forceinline__ void init_block(const ReqDesc& rq) {
       const int b = nb - 1 - pos;
       const int row_end = min(n, (b + 1) * kBandRows);
       const int nt = (row_end + kTile - 1) / kTile;
-      const int ch = (nt + L - 1) / L;
+      const int Lb = item_tiles(b, b_fine, L);
+      const int ch = (nt + Lb - 1) / Lb;
       glb(rq.band)[b].x = base;
       glb(rq.band)[b].y = ch;
       for (int c = 0; c < ch; ++c) { glb(rq.items)[base + c].x = b; glb(rq.items)[base + c].y = c; }
@@ -351,8 +353,9 @@ __global__ void __launch_bounds__(kThreads) k_pass1(const ReqDesc* __restrict__ 
   const int row_base = band * kBandRows;
   const int row_end = min(kp.n, row_base + kBandRows);
   const int nt_band = (row_end + kTile - 1) / kTile;
-  const int tile0 = chunk * kp.L;
-  const int tile1 = min(tile0 + kp.L, nt_band);
+  const int Lb = item_tiles(band, kp.b_fine, kp.L);
+  const int tile0 = chunk * Lb;
+  const int tile1 = min(tile0 + Lb, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
   const int first_min = uni(first[row_base]);
   const auto t_row0 = rec[row_base].v[D];   // the band's first row (culling)
@@ -505,8 +508,9 @@ __global__ void __launch_bounds__(kThreads) k_pass2(const ReqDesc* __restrict__ 
   const int row_base = band * kBandRows;
   const int row_end = min(kp.n, row_base + kBandRows);
   const int nt_band = (row_end + kTile - 1) / kTile;
-  const int tile0 = chunk * kp.L;
-  const int tile1 = min(tile0 + kp.L, nt_band);
+  const int Lb = item_tiles(band, kp.b_fine, kp.L);
+  const int tile0 = chunk * Lb;
+  const int tile1 = min(tile0 + Lb, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
   const int first_min = uni(first[row_base]);
   const auto t_row0 = rec[row_base].v[D];   // the band's first row (culling)
@@ -727,8 +731,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(r
   const int row_base = band * kBandRows;
   const int row_end = min(kp.n, row_base + kBandRows);
   const int nt_band = (row_end + kTile - 1) / kTile;
-  const int tile0 = chunk * kp.L;
-  const int tile1 = min(tile0 + kp.L, nt_band);
+  const int Lb = item_tiles(band, kp.b_fine, kp.L);
+  const int tile0 = chunk * Lb;
+  const int tile1 = min(tile0 + Lb, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
   const int first_min = uni(first[row_base]);
   const double t_row0 = glb(rq.t)[row_base];   // the band's first row (culling)
@@ -916,8 +921,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(g
   const int row_base = band * kBandRows;
   const int row_end = min(kp.n, row_base + kBandRows);
   const int nt_band = (row_end + kTile - 1) / kTile;
-  const int tile0 = chunk * kp.L;
-  const int tile1 = min(tile0 + kp.L, nt_band);
+  const int Lb = item_tiles(band, kp.b_fine, kp.L);
+  const int tile0 = chunk * Lb;
+  const int tile1 = min(tile0 + Lb, nt_band);
   const bool partial_band = row_base + kBandRows > kp.n;
   const int first_min = uni(first[row_base]);
   const double t_row0 = glb(rq.t)[row_base];   // the band's first row (culling)
