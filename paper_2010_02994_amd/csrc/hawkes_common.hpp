@@ -162,37 +162,22 @@ struct ReqDesc {
 };
 
 // Float64 exp of the pair passes and the Metropolis kernels, by Tang's table-driven method (P. T. P. Tang,
-// ACM Trans. Math. Softw. 15(2), 1989) with 2^B table entries tab[j] = 2^(j/2^B)
-// held in LDS: z = (2^B m + j) ln2/2^B + r with |r| <= ln2/2^(B+1), and
-// exp(z) = 2^m tab[j] (1 + p(r)), p the Taylor polynomial of expm1 of degree 5
-// (B = 6) or 4 (B = 8), truncated below 4e-17 relative either way.  The
-// reduction subtracts k ln2/2^B in two fused steps (ln2/2^B split into a double
-// and its remainder), so r is exact to ~1e-18.  ldexp rounds once, also into
-// the subnormal range.  Arguments are first clamped at -1100: exp is 0 below
-// -746, ldexp returns exactly 0 for such scales, and the clamp keeps k in range
-// (and maps -inf to 0).
-#ifndef HK_FP64_EXP_TABLE
-#define HK_FP64_EXP_TABLE 1
-#endif
-#ifndef HK_FP64_EXP_BITS
-#define HK_FP64_EXP_BITS 8
-#endif
-constexpr int kExpTab = 1 << HK_FP64_EXP_BITS;
+// ACM Trans. Math. Softw. 15(2), 1989) with 2^8 table entries tab[j] = 2^(j/256)
+// held in LDS: z = (256 m + j) ln2/256 + r with |r| <= ln2/512, and
+// exp(z) = 2^m tab[j] (1 + p(r)), p the Taylor polynomial of expm1 of degree 4,
+// truncated below 4e-17 relative.  The reduction subtracts k ln2/256 in two
+// fused steps (ln2/256 split into a double and its remainder), so r is exact
+// to ~1e-18.  ldexp rounds once, also into the subnormal range.  Arguments are
+// first clamped at -1100: exp is 0 below -746, ldexp returns exactly 0 for
+// such scales, and the clamp keeps k in range (and maps -inf to 0).
+constexpr int kExpBits = 8;
+constexpr int kExpTab = 1 << kExpBits;
 __device__ __forceinline__ double exp_tab(double z, const double* __restrict__ tab) {
-#if HK_FP64_EXP_TABLE
-#if HK_FP64_EXP_BITS == 6
-  constexpr double kInvStep = 92.33248261689366;        // 64 / ln2
-  constexpr double kStepHi = 0x1.62e42fefa39efp-7;       // ln2 / 64, rounded
-  constexpr double kStepLo = 0x1.abc9e3b39803fp-62;      // ln2 / 64 - kStepHi
-#elif HK_FP64_EXP_BITS == 8
   constexpr double kInvStep = 369.3299304675746;        // 256 / ln2
   constexpr double kStepHi = 0x1.62e42fefa39efp-9;       // ln2 / 256, rounded
   constexpr double kStepLo = 0x1.abc9e3b39803fp-64;      // ln2 / 256 - kStepHi
-#else
-#error "HK_FP64_EXP_BITS must be 6 or 8"
-#endif
   z = __builtin_fmax(z, -1100.0);
-  // k = z 2^B/ln2 rounded to an integer by adding 1.5 * 2^52 (the sum's unit
+  // k = z 2^8/ln2 rounded to an integer by adding 1.5 * 2^52 (the sum's unit
   // in the last place is 1, so the low word of its bits is k in two's
   // complement; exact for |k| < 2^31, and |k| < 410,000 after the clamp)
   constexpr double kRound = 0x1.8p52;
@@ -201,21 +186,12 @@ __device__ __forceinline__ double exp_tab(double z, const double* __restrict__ t
   const double kf = kb - kRound;
   double r = __builtin_fma(-kf, kStepHi, z);
   r = __builtin_fma(-kf, kStepLo, r);
-#if HK_FP64_EXP_BITS == 6
-  double p = __builtin_fma(r, 1.0 / 120.0, 1.0 / 24.0);
-  p = __builtin_fma(r, p, 1.0 / 6.0);
-#else
   double p = __builtin_fma(r, 1.0 / 24.0, 1.0 / 6.0);
-#endif
   p = __builtin_fma(r, p, 0.5);
   p = __builtin_fma(r, p, 1.0);
   p = r * p;
   const double tj = tab[k & (kExpTab - 1)];
-  return __builtin_ldexp(__builtin_fma(tj, p, tj), k >> HK_FP64_EXP_BITS);
-#else
-  (void)tab;
-  return exp(z);
-#endif
+  return __builtin_ldexp(__builtin_fma(tj, p, tj), k >> kExpBits);
 }
 
 // Fills the table of exp_tab; the caller synchronizes the workgroup before
