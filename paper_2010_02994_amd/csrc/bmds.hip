@@ -409,7 +409,12 @@ constexpr int kPackThreads = 256;
 #ifndef HK_BMDS_STRIP_COLS_FP64
 #define HK_BMDS_STRIP_COLS_FP64 2
 #endif
-// bands per segment: 1, 2, 4 or a multiple of 4
+// Bands per segment: 1, 2, 4 or a multiple of 4.  Float32 pairs take one band
+// (a tile per workgroup: at N = 20,000 the many short workgroups balance the
+// chip better than longer column sums save writes; 2, 4 and 8 bands were 1 %,
+// 10 % and 35 % slower), float64 pairs two.  The ring holds two rows for
+// float32 pairs (four rows: 17 more registers, one wave per SIMD fewer,
+// slower) and four for float64 pairs.
 constexpr bool valid_strip_k(int k) { return k == 1 || k == 2 || (k >= 4 && k % 4 == 0); }
 constexpr int kStripKMixed = HK_BMDS_STRIP_K_MIXED;
 constexpr int kStripKFp64 = HK_BMDS_STRIP_K_FP64;
