@@ -411,10 +411,11 @@ constexpr int kPackThreads = 256;
 #endif
 // Bands per segment: 1, 2, 4 or a multiple of 4.  Float32 pairs take one band
 // (a tile per workgroup: at N = 20,000 the many short workgroups balance the
-// chip better than longer column sums save writes; 2, 4 and 8 bands were 1 %,
-// 10 % and 35 % slower), float64 pairs two.  The ring holds two rows for
-// float32 pairs (four rows: 17 more registers, one wave per SIMD fewer,
-// slower) and four for float64 pairs.
+// chip better than longer column sums save writes; two bands measured from
+// 1 % faster to 9 % slower in two runs, four 8 % slower, eight 35 % slower),
+// float64 pairs two.  The ring holds two rows for float32 pairs (four rows:
+// 17 more registers, one wave per SIMD fewer, 5 % slower) and four for
+// float64 pairs.
 constexpr bool valid_strip_k(int k) { return k == 1 || k == 2 || (k >= 4 && k % 4 == 0); }
 constexpr int kStripKMixed = HK_BMDS_STRIP_K_MIXED;
 constexpr int kStripKFp64 = HK_BMDS_STRIP_K_FP64;
