@@ -30,13 +30,18 @@ static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // bands' items run last.  Split into one-tile items, they end the launch with
 // short workgroups, so the chip drains in about a tile's time instead of an
 // item's.  The split covers the first bands whose tiles total at most
-// kTailTiles (about one round of the chip's concurrent workgroups).
+// kTailTiles (about one round of the chip's concurrent workgroups), in
+// launches of at least 8 kTailTiles tiles (N >~ 36,000), where that tail is a
+// small share of the work; smaller launches keep their measured item sizes.
 #ifndef HK_TAIL_TILES
 #define HK_TAIL_TILES 1280
 #endif
 constexpr int64_t kTailTiles = HK_TAIL_TILES;
 static int fine_bands(int64_t n, int nb, int L) {
   if (L <= 1) return 0;
+  int64_t all = 0;
+  for (int b = 0; b < nb; ++b) all += (std::min<int64_t>(n, (int64_t)(b + 1) * kBandRows) + kTile - 1) / kTile;
+  if (all < 8 * kTailTiles) return 0;
   int64_t tiles = 0;
   int b = 0;
   for (; b < nb; ++b) {
