@@ -76,20 +76,19 @@ def test_bmds_deterministic():
 _big = {}
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("d", [6, 2])
-def test_bmds_many_tiles_matches_oracle(prec, d):
-    """N = 12,000 (over 4,096 tiles, so several columns per lane)."""
+def _check_device_case(key, seed, n, d, prec):
+    """Device-drawn case of size n (5 % unobserved), the oracle's result
+    cached per (n, d) across the precisions."""
     import torch
     from paper_2010_02994_amd import api
-    if _big.get("d") != d:
+    if _big.get("key") != key:
         _big.clear()
-        x, dl, sigma = W.bmds_case_device(9 + d, 12000, d, missing=0.05)
-        _big.update(d=d, case=(x, dl, sigma), ref=oracle.bmds(x.cpu().numpy(), dl.cpu().numpy(), sigma))
+        x, dl, sigma = W.bmds_case_device(seed, n, d, missing=0.05)
+        _big.update(key=key, case=(x, dl, sigma), ref=oracle.bmds(x.cpu().numpy(), dl.cpu().numpy(), sigma))
     x, dl, sigma = _big["case"]
     st, ll, ds, M, gx_ref = _big["ref"]
     assert st == 0
-    say(f"case bmds n=12000 d={d} prec={prec}")
+    say(f"case bmds n={n} d={d} prec={prec}")
     out4, gxd = api.bmds(x, dl, sigma, prec=prec)
     torch.cuda.synchronize()
     o, gx = out4.cpu().numpy(), gxd.cpu().numpy()
@@ -100,3 +99,20 @@ def test_bmds_many_tiles_matches_oracle(prec, d):
     t = TOL[prec]
     assert o[3] == 0 and o[2] == M
     assert e_ll <= t["ll"] and e_ds <= t["ds"] and e_gx <= t["gx"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("d", [6, 2])
+def test_bmds_many_tiles_matches_oracle(prec, d):
+    """N = 12,000 (over 4,096 tiles, so several columns per lane)."""
+    _check_device_case(("many", d), 9 + d, 12000, d, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [11456, 11457])
+def test_bmds_tile_count_boundary(prec, n):
+    """Either side of the 4,096-tile switch: N = 11,456 is the largest with
+    fewer tiles (179 bands, 4,095 tiles: one workgroup per tile for float64
+    pairs, single-band strips of one column per lane for float32 pairs), and
+    N = 11,457 the smallest with more (the wide strips)."""
+    _check_device_case(("edge", n), 30 + n % 7, n, 3, prec)
