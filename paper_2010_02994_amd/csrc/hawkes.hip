@@ -322,6 +322,59 @@ static ForkPool& fork_pool() {
 Fork* fork_take(int dev, bool allow_create) { return fork_pool().take(dev, allow_create); }
 void fork_give(int dev, Fork* f) { fork_pool().give(dev, f); }
 
+// Host-pinned result buffers of eight doubles, mapped into the device's
+// address space (coherent: the device's stores bypass its caches), pooled
+// for the life of the process.  The last kernel of a synchronous gradient
+// call writes out8 there, so the call reads its scalars after the stream
+// synchronization with no device-to-host copy.  A buffer is held by one call
+// at a time.
+struct Pinned {
+  double* host = nullptr;
+  double* dev = nullptr;
+};
+class PinnedPool {
+ public:
+  Pinned take(bool allow_create) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (!free_.empty()) {
+        const Pinned p = free_.back();
+        free_.pop_back();
+        return p;
+      }
+    }
+    Pinned p;
+    if (!allow_create) return p;
+    void* h = nullptr;
+    void* d = nullptr;
+    if (hipHostMalloc(&h, 8 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      return p;
+    }
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess || d == nullptr) {
+      (void)hipGetLastError();
+      (void)hipHostFree(h);
+      return p;
+    }
+    p.host = static_cast<double*>(h);
+    p.dev = static_cast<double*>(d);
+    return p;
+  }
+  void give(const Pinned& p) {
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.push_back(p);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<Pinned> free_;
+};
+static PinnedPool& pinned_pool() {
+  static PinnedPool* p = new PinnedPool();   // never destroyed, like the side streams
+  return *p;
+}
+
 // The phases over every request of a batch (all with the same D and
 // precision).  reqs: device array of descriptors; totals: grid sizes.
 // fk == nullptr: everything in order on s (used when stages are timed).
@@ -444,7 +497,7 @@ static int check_args(const double* x, const double* t, int64_t n, int d, const 
 }
 
 int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
-              size_t ws_bytes, void* stream, double* out8, double* grad_x, double* terms) {
+              size_t ws_bytes, void* stream, double* out8, double* grad_x, double* terms, double* out_host) {
   Layout Lo;
   const int st = check_args(x, t, n, d, p, prec, ws, ws_bytes, Lo);
   if (st != HAWKES_OK) return st;
@@ -453,6 +506,7 @@ int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_p
   hipStream_t s = static_cast<hipStream_t>(stream);
   ReqDesc desc = make_desc(Lo, kp, x, t, ws, out8, grad_x);
   desc.terms = terms;
+  desc.out_host = grad_x ? out_host : nullptr;   // written by k_reduce2, which only gradient calls run
   const BatchGrid g = assign_blocks(&desc, 1);
   ReqDesc* dev = at<ReqDesc>(ws, Lo.off_desc);
   return launch_batch(d, Lo.mixed, dev, 1, g, grad_x != nullptr, s, &desc);
@@ -463,12 +517,27 @@ int run_sync(const double* x, const double* t, int64_t n, int d, const hawkes_pa
   Layout Lo;
   if (!ws || !make_layout(n, d, prec, Lo)) return HAWKES_EINVAL;
   double* out8 = at<double>(ws, Lo.off_out8);
-  int st = run_async(x, t, n, d, p, prec, ws, ws_bytes, stream, out8, grad_x, terms);
-  if (st != HAWKES_OK) return st;
+  // gradient calls take the scalars from a pinned buffer that their last
+  // kernel writes (none is created while allocation is barred)
+  const Pinned pin = grad_x ? pinned_pool().take(!g_no_create) : Pinned{};
+  if (pin.host)
+    for (int q = 0; q < 8; ++q) pin.host[q] = NAN;   // a status the kernel did not write reads as a device error
+  int st = run_async(x, t, n, d, p, prec, ws, ws_bytes, stream, out8, grad_x, terms, pin.dev);
+  if (st != HAWKES_OK) {
+    if (pin.host) pinned_pool().give(pin);
+    return st;
+  }
   double h[8];
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (hipMemcpyAsync(h, out8, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return HAWKES_EDEVICE;
-  if (hipStreamSynchronize(s) != hipSuccess) return HAWKES_EDEVICE;
+  if (pin.host) {
+    const bool ok = hipStreamSynchronize(s) == hipSuccess;
+    for (int q = 0; q < 8; ++q) h[q] = static_cast<volatile double*>(pin.host)[q];
+    pinned_pool().give(pin);
+    if (!ok || std::isnan(h[7])) return HAWKES_EDEVICE;
+  } else {
+    if (hipMemcpyAsync(h, out8, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return HAWKES_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return HAWKES_EDEVICE;
+  }
   st = (int)h[7];
   if (st == HAWKES_EDATA) return st;
   if (loglik) *loglik = h[0];

@@ -155,6 +155,7 @@ struct ReqDesc {
   double* fixpart;
   double* terms;    // optional, n x 4: per-event terms written by k_final1 (null: none)
   double* mompart;  // items x 2: per-item moment sums of the mixed gradient pass
+  double* out_host; // optional host-pinned copy of out8, written by the gradient call's last kernel (null: none)
   int blk_items;    // first block of this request in a pair-pass launch
   int blk_ev;       // first block in a per-event launch (kEvBlock events per block)
   int blk_pad;      // first block in the pack launch (n_pad / kEvBlock blocks)

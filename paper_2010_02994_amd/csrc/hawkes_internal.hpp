@@ -37,8 +37,11 @@ int launch_batch(int d, int mixed, const ReqDesc* dev_reqs, int nreq, const Batc
                  const ReqDesc* one = nullptr);
 // Enqueue one full evaluation (validation, rate pass, finalize and, when
 // grad_x is not null, the gradient pass) with no host synchronization.
+// out_host (gradient calls only; may be null): device-visible pinned memory
+// that the last kernel also writes out8 to.
 int run_async(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
-              size_t ws_bytes, void* stream, double* out8, double* grad_x, double* terms = nullptr);
+              size_t ws_bytes, void* stream, double* out8, double* grad_x, double* terms = nullptr,
+              double* out_host = nullptr);
 // run_async, then the scalars to the host (stream synchronized).
 int run_sync(const double* x, const double* t, int64_t n, int d, const hawkes_params_t* p, int prec, void* ws,
              size_t ws_bytes, void* stream, double* loglik, double* grad_x, double* grad_params,

@@ -1419,8 +1419,13 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce2(const ReqDesc* __restri
   const int rid = find_req(reqs, nreq, blockIdx.x, 3);
   const ReqDesc& rq = reqs[rid];
   const KParams& kp = rq.kp;
-  if (uni(glb(rq.status)[kStData]) != 0) return;
-  if (MIX && !kp.ru1 && (int)blockIdx.x == rq.blk_red) {
+  // the request's first workgroup completes out8 (and its host copy)
+  const bool head = (int)blockIdx.x == rq.blk_red;
+  if (uni(glb(rq.status)[kStData]) != 0) {
+    if (head && rq.out_host && threadIdx.x < 8) rq.out_host[threadIdx.x] = glb(rq.out8)[threadIdx.x];
+    return;
+  }
+  if (MIX && !kp.ru1 && head) {
     // the background moments' terms of d ell/d tau_x and d ell/d tau_t, from
     // the gradient pass's item sums in item order: sum over pairs of
     // w r'^2 = sum_n c_bg R_n / (tau_x^3 lambda_n) and w dt'^2 tau_x / tau_t =
@@ -1452,6 +1457,9 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce2(const ReqDesc* __restri
       glb(rq.out8)[3] += m1 * kp.tau_x / kp.tau_t;
     }
   }
+  if (head && rq.out_host && threadIdx.x == 0)   // the thread that added the moment terms
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rq.out_host[q] = glb(rq.out8)[q];
   if (rq.grad_x == nullptr) return;
   const auto grad_x = glb(rq.grad_x);
   const int lb = blockIdx.x - rq.blk_red;
