@@ -136,44 +136,55 @@ __device__ __forceinline__ void init_block(const ReqDesc& rq) {
     for (int k = 0; k < D; ++k) glb(rq.dconst)[1 + k] = 0.5 * (x[k] + x[(int64_t)(n - 1) * D + k]);
     glb(rq.dconst)[1 + kMaxD] = 0.5 * (t[0] + t[n - 1]);
   }
-  const int per = (nb + 1023) / 1024;
-  int local = 0;
-  for (int q = 0; q < per; ++q) {
-    const int pos = tid * per + q;
-    if (pos < nb) {
-      const int b = nb - 1 - pos;
-      const int row_end = min(n, (b + 1) * kBandRows);
-      const int nt = (row_end + kTile - 1) / kTile;
-      const int Lb = item_tiles(b, b_fine, L);
-      local += (nt + Lb - 1) / Lb;
-    }
-  }
-  // exclusive scan of the item counts: within each wave by shuffles, then
-  // the totals of the earlier waves (one barrier instead of twenty)
+  // the bands in rounds of 1024 positions (position p = band nb - 1 - p):
+  // every thread counts one band's items, an exclusive scan over the round
+  // (wave shuffles, then the earlier waves' totals) gives each band its first
+  // item, and the waves then write the round's items, each band's by
+  // consecutive lanes
+  __shared__ int s_b[1024], s_base[1024], s_ch[1024];
   const int lane = tid & 63, wv = tid >> 6;
-  int incl = local;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int v = __shfl_up(incl, off);
-    if (lane >= off) incl += v;
-  }
-  if (lane == 63) s_wsum[wv] = incl;
-  __syncthreads();
-  int base = incl - local;
-  for (int w2 = 0; w2 < wv; ++w2) base += s_wsum[w2];
-  for (int q = 0; q < per; ++q) {
-    const int pos = tid * per + q;
+  int carry = 0;   // items of the earlier rounds
+  for (int r0 = 0; r0 < nb; r0 += 1024) {
+    const int pos = r0 + tid;
+    int b = 0, ch = 0;
     if (pos < nb) {
-      const int b = nb - 1 - pos;
+      b = nb - 1 - pos;
       const int row_end = min(n, (b + 1) * kBandRows);
       const int nt = (row_end + kTile - 1) / kTile;
       const int Lb = item_tiles(b, b_fine, L);
-      const int ch = (nt + Lb - 1) / Lb;
+      ch = (nt + Lb - 1) / Lb;
+    }
+    int incl = ch;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off);
+      if (lane >= off) incl += v;
+    }
+    if (lane == 63) s_wsum[wv] = incl;
+    __syncthreads();
+    int base = carry + incl - ch, total = 0;
+    for (int w2 = 0; w2 < 1024 / 64; ++w2) {
+      if (w2 < wv) base += s_wsum[w2];
+      total += s_wsum[w2];
+    }
+    s_b[tid] = b;
+    s_base[tid] = base;
+    s_ch[tid] = ch;
+    if (pos < nb) {
       glb(rq.band)[b].x = base;
       glb(rq.band)[b].y = ch;
-      for (int c = 0; c < ch; ++c) { glb(rq.items)[base + c].x = b; glb(rq.items)[base + c].y = c; }
-      base += ch;
     }
+    __syncthreads();
+    const int cnt = min(1024, nb - r0);
+    for (int p = wv; p < cnt; p += 1024 / 64) {
+      const int bp = s_b[p], bs = s_base[p], cp = s_ch[p];
+      for (int c = lane; c < cp; c += 64) {
+        glb(rq.items)[bs + c].x = bp;
+        glb(rq.items)[bs + c].y = c;
+      }
+    }
+    carry += total;
+    __syncthreads();   // s_wsum and the round's tables are reused
   }
 }
 
