@@ -85,7 +85,10 @@ int hawkes_loglik(const double* x, const double* t, int64_t n, int d, const hawk
 
 /* Log-likelihood and full gradient.  grad_x: device, n*d row-major, overwritten.
  * loglik (host, 1) and grad_params (host, 6, API order) receive the scalars;
- * either may be NULL.  Synchronizes the stream to deliver them.
+ * either may be NULL.  Synchronizes the stream to deliver them; the last
+ * kernel writes them to a library-owned pinned host buffer of 64 bytes (one
+ * per concurrent call, kept until the process ends), read after the
+ * synchronization.
  * Gradient calls also use a library-owned side stream (non-blocking, default
  * priority; one per concurrent caller, kept until the process ends): the
  * float64 fix-ups and the finalize kernels run there while the gradient pass
