@@ -44,12 +44,14 @@ def _lib(threads: bool):
         i64 = ctypes.c_int64
         lib.oracle_loglik_grad.argtypes = [d, d, i64, ctypes.c_int, d, d, d, d]
         lib.oracle_rates.argtypes = [d, d, i64, ctypes.c_int, d, d, d]
+        lib.oracle_rate_rows.argtypes = [d, d, i64, ctypes.c_int, d, ctypes.POINTER(i64), i64, d, d]
         lib.oracle_grad_rows.argtypes = [d, d, i64, ctypes.c_int, d, d, ctypes.POINTER(i64), i64, d]
         lib.oracle_grad_rows_scaled.argtypes = [d, d, i64, ctypes.c_int, d, d, ctypes.POINTER(i64), i64, d, d]
         lib.oracle_log_rates.argtypes = [d, d, i64, ctypes.c_int, d, d, d]
         lib.oracle_param_terms.argtypes = [d, d, i64, ctypes.c_int, d, d, d]
         lib.oracle_bmds.argtypes = [d, d, i64, ctypes.c_int, ctypes.c_double, d, d]
-        for f in (lib.oracle_loglik_grad, lib.oracle_rates, lib.oracle_grad_rows, lib.oracle_grad_rows_scaled,
+        for f in (lib.oracle_loglik_grad, lib.oracle_rates, lib.oracle_rate_rows, lib.oracle_grad_rows,
+                  lib.oracle_grad_rows_scaled,
                   lib.oracle_log_rates, lib.oracle_param_terms, lib.oracle_bmds):
             f.restype = ctypes.c_int
         _libs[key] = lib
@@ -90,6 +92,22 @@ def rates(x, t, params, threads: bool = False):
     st = _lib(threads).oracle_rates(_p(x), _p(t), n, d, _p(p), _p(lam), _p(s6))
     if st != 0:
         raise ValueError(f"oracle_rates status {st}")
+    return lam, s6
+
+
+def rate_rows(x, t, params, rows, threads: bool = True):
+    """(lambda, row sums K,R,U,J,V,W) of the listed events only: the per-event
+    sums of `rates`, O(N) per listed event, for spot checks of large inputs."""
+    x, t, p = _prep(x, t, params)
+    n, d = x.shape
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    lam = np.zeros(rows.shape[0])
+    s6 = np.zeros((rows.shape[0], 6))
+    st = _lib(threads).oracle_rate_rows(_p(x), _p(t), n, d, _p(p),
+                                        rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), rows.shape[0],
+                                        _p(lam), _p(s6))
+    if st != 0:
+        raise ValueError(f"oracle_rate_rows status {st}")
     return lam, s6
 
 

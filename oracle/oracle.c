@@ -134,6 +134,28 @@ int oracle_rates(const double* x, const double* t, int64_t n, int d, const doubl
   return ORACLE_OK;
 }
 
+/* The rates (Sec. 2.1) of the events listed in rows[], and their unweighted
+ * row sums if sums6 is not NULL: the same per-event sums as oracle_rates,
+ * O(n) work per listed event, for spot checks of inputs too large for the
+ * full evaluation.  Every listed index must lie in [0, n). */
+int oracle_rate_rows(const double* x, const double* t, int64_t n, int d, const double* theta6,
+                     const int64_t* rows, int64_t nrows, double* lam, double* sums6) {
+  model m;
+  if (n < 1 || d < 1 || !x || !t || !rows || !lam || nrows < 0) return ORACLE_EINVAL;
+  if (make_model(theta6, d, &m) != ORACLE_OK) return ORACLE_EINVAL;
+  for (int64_t r = 0; r < nrows; ++r)
+    if (rows[r] < 0 || rows[r] >= n) return ORACLE_EINVAL;
+  int64_t r;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (r = 0; r < nrows; ++r) {
+    double s6[6];
+    row_sums(&m, x, t, n, rows[r], s6);
+    lam[r] = row_rate(&m, s6);
+    if (sums6) memcpy(sums6 + 6 * r, s6, sizeof(s6));
+  }
+  return ORACLE_OK;
+}
+
 /* Location gradient rows (App. A) for the events listed in rows[], given the
  * rates lam[] of all events.  A partner whose three pair terms are exactly
  * zero adds exactly zero, so its rate is not needed beyond being finite.

@@ -286,6 +286,31 @@ def test_zero_rate_is_flagged():
     assert st == oracle.ZERORATE and ll == -math.inf
 
 
+@pytest.mark.parametrize("seed,n,d", [(1, 2, 1), (4, 6, 3)])
+def test_rate_rows_match_rate_functions_mpmath(seed, n, d):
+    """rate_rows: the rates of listed events (in any order) equal mu + xi of
+    Sec. 2.1 evaluated at 50 digits."""
+    w = _case(seed, n, d, t_span=3.0)
+    rows = np.arange(n)[::-1]
+    lam, _ = oracle.rate_rows(w.x, w.t, w.params, rows)
+    ref = R.rates_at_events(w.x.tolist(), w.t.tolist(), w.params.tolist())
+    for r, a in zip(rows, lam):
+        assert abs(a - float(ref[r])) <= 1e-14 * abs(float(ref[r]))
+
+
+def test_rate_rows_equal_rates():
+    """rate_rows gives the full evaluation's rates and row sums bit for bit
+    (single-threaded and threaded builds), and refuses an index outside [0, n)."""
+    w = _case(131, 60, 2, ties=3, t_span=3.0)
+    lam, s6 = oracle.rates(w.x, w.t, w.params)
+    rows = np.array([0, 59, 17, 17, 31])
+    for threads in (False, True):
+        l2, s2 = oracle.rate_rows(w.x, w.t, w.params, rows, threads=threads)
+        assert np.array_equal(l2, lam[rows]) and np.array_equal(s2, s6[rows])
+    with pytest.raises(ValueError):
+        oracle.rate_rows(w.x, w.t, w.params, [60])
+
+
 def test_grad_rows_equals_full_gradient():
     w = _case(130, 50, 2, ties=2, t_span=3.0)
     st, ll, gx, gp = oracle.loglik_grad(w.x, w.t, w.params)
