@@ -179,12 +179,16 @@ def diagnostics(x, t, params, threads: bool = True, log_floor: float = FLT_MIN_L
 # log-likelihood routines, so it checks the incremental GPU path against a full
 # recomputation.
 
-def event_terms(x, t, params, threads: bool = True):
+def event_terms(x, t, params, threads: bool = True, rows=None):
     """(N, 4): background rate per unit mu0, self-excitation rate per unit
     theta, log lambda, and theta * b / lambda (the self-excitation share of the
-    rate, i.e. the probability that the event has a parent)."""
+    rate, i.e. the probability that the event has a parent).  rows: only
+    those events, in that order (O(N) each)."""
     p = np.asarray(params, dtype=np.float64)
-    lam, s6 = rates(x, t, p, threads=threads)
+    if rows is None:
+        lam, s6 = rates(x, t, p, threads=threads)
+    else:
+        lam, s6 = rate_rows(x, t, p, rows, threads=threads)
     out = np.empty((lam.shape[0], 4))
     out[:, 0] = s6[:, 0]
     out[:, 1] = s6[:, 3]

@@ -68,6 +68,28 @@ def test_event_terms_d6_and_isolated_rows(prec):
     _check_terms(terms.cpu().numpy(), oracle.event_terms(x, w.t, w.params), prec, w.params, "d6")
 
 
+_n530 = {}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_event_terms_more_than_1024_bands(prec):
+    """N = 530,000 (1,036 row bands of 512 events, so the set-up kernel lays
+    out the work items in two rounds of 1,024 bands; the second round holds
+    bands 11 down to 0): the per-event terms of about 60 events, from the
+    first band to the last, against the oracle's rates of those events alone."""
+    from paper_2010_02994_amd import api
+    if not _n530:
+        w = W.config2(n=530000)
+        rng = np.random.default_rng(530)
+        rows = np.unique(np.concatenate([[0, 1, 511, 512, 6143, 6144, w.n - 1], rng.integers(0, 6144, 10),
+                                         rng.integers(0, w.n, 40)]))
+        _n530.update(w=w, rows=rows, ref=oracle.event_terms(w.x, w.t, w.params, rows=rows))
+    w, rows, ref = _n530["w"], _n530["rows"], _n530["ref"]
+    say(f"case event-terms n={w.n} rows={len(rows)} prec={prec}")
+    terms, _ = api.event_terms(_dev(w.x), _dev(w.t), w.params, prec=prec)
+    _check_terms(terms.cpu().numpy()[rows], ref, prec, w.params, "n530000")
+
+
 def _state(w, x=None):
     from paper_2010_02994_amd import api
     x = w.x if x is None else x
