@@ -19,11 +19,11 @@ def _dev(a, dtype=None):
     return torch.tensor(np.ascontiguousarray(a), device="cuda:0", dtype=dtype)
 
 
-def _check_terms(got, ref, prec, params, label=""):
-    """float64: each of a, b to 1e-10 of itself.  Mixed: a and b to 2e-5 of the
-    rate they form (a part far below its row's rate lies under the float32
-    window and may read 0); log lambda and the probability absolutely."""
-    tol = 1e-10 if prec == "fp64" else 2e-5
+def _check_terms(got, ref, prec, params, label="", mixed_tol=2e-5):
+    """float64: each of a, b to 1e-10 of itself.  Mixed: a and b to mixed_tol
+    of the rate they form (a part far below its row's rate lies under the
+    float32 window and may read 0); log lambda and the probability absolutely."""
+    tol = 1e-10 if prec == "fp64" else mixed_tol
     ok = np.isfinite(ref[:, 2])
     mu0, th = params[0], params[3]
     if prec == "fp64":
@@ -75,19 +75,23 @@ _n530 = {}
 def test_event_terms_more_than_1024_bands(prec):
     """N = 530,000 (1,036 row bands of 512 events, so the set-up kernel lays
     out the work items in two rounds of 1,024 bands; the second round holds
-    bands 11 down to 0): the per-event terms of about 60 events, from the
-    first band to the last, against the oracle's rates of those events alone."""
+    bands 11 down to 0): the per-event terms of about 200 events, from the
+    first band to the last, against the oracle's rates of those events alone.
+    The wildfire-like events span ~250 bandwidths, so in mixed precision a
+    pair term carries a relative error up to ~1e-4 from the float32
+    coordinates, and a rate, a weighted mean of its terms' errors, is held to
+    the worst-row bar of 3e-4 of the gradient rows."""
     from paper_2010_02994_amd import api
     if not _n530:
         w = W.config2(n=530000)
         rng = np.random.default_rng(530)
-        rows = np.unique(np.concatenate([[0, 1, 511, 512, 6143, 6144, w.n - 1], rng.integers(0, 6144, 10),
-                                         rng.integers(0, w.n, 40)]))
+        rows = np.unique(np.concatenate([[0, 1, 511, 512, 6143, 6144, w.n - 1], rng.integers(0, 6144, 20),
+                                         rng.integers(0, w.n, 180)]))
         _n530.update(w=w, rows=rows, ref=oracle.event_terms(w.x, w.t, w.params, rows=rows))
     w, rows, ref = _n530["w"], _n530["rows"], _n530["ref"]
     say(f"case event-terms n={w.n} rows={len(rows)} prec={prec}")
     terms, _ = api.event_terms(_dev(w.x), _dev(w.t), w.params, prec=prec)
-    _check_terms(terms.cpu().numpy()[rows], ref, prec, w.params, "n530000")
+    _check_terms(terms.cpu().numpy()[rows], ref, prec, w.params, "n530000", mixed_tol=3e-4)
 
 
 def _state(w, x=None):
