@@ -340,6 +340,46 @@ def test_side_stream_matches_in_order(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_sync_scalars_equal_async_out8(prec):
+    """hawkes_grad delivers its scalars through a pinned buffer that its last
+    kernel writes: they equal hawkes_grad_async's device out8 bit for bit, the
+    host outputs may be NULL, and a following call with other data gets its
+    own values."""
+    import ctypes
+    import torch
+    from paper_2010_02994_amd import _lib, api
+    L = _lib.lib()
+    for w in (W.random_case(81, 3000, 2, ties=2, t_span=30.0), W.random_case(82, 700, 3)):
+        say(f"case sync scalars vs async out8 n={w.n} prec={prec}")
+        x = torch.tensor(w.x, device="cuda:0")
+        t = torch.tensor(w.t, device="cuda:0")
+        n, d = x.shape
+        ws = api.workspace(n, d, prec, x.device)
+        ps = api.params_struct(w.params)
+        s = api._stream_ptr(x.device)
+        gx_a = torch.empty_like(x)
+        out8 = torch.full((8,), float("nan"), dtype=torch.float64, device="cuda:0")
+        st = L.hawkes_grad_async(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), api._prec(prec), ws.data_ptr(),
+                                 ws.numel(), s, out8.data_ptr(), gx_a.data_ptr())
+        assert st == 0, _lib.strerror(st)
+        torch.cuda.synchronize()
+        o = out8.cpu().numpy()
+        ll = ctypes.c_double(float("nan"))
+        gp = (ctypes.c_double * 6)()
+        gx = torch.empty_like(x)
+        st = L.hawkes_grad(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), api._prec(prec), ws.data_ptr(),
+                           ws.numel(), s, ctypes.byref(ll), gx.data_ptr(), gp)
+        assert st == 0, _lib.strerror(st)
+        assert o[7] == 0.0 and ll.value == o[0] and np.array_equal(np.array(gp[:]), o[1:7])
+        gx2 = torch.empty_like(x)
+        st = L.hawkes_grad(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), api._prec(prec), ws.data_ptr(),
+                           ws.numel(), s, None, gx2.data_ptr(), None)
+        assert st == 0, _lib.strerror(st)
+        torch.cuda.synchronize()
+        assert torch.equal(gx, gx_a) and torch.equal(gx2, gx_a)
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_concurrent_callers_on_own_streams(prec):
     """Four host threads, each on its own stream with its own data, call
     hawkes_grad three times; every result equals a lone call's bit for bit."""
