@@ -50,7 +50,9 @@ typedef struct {
 } hawkes_params_t;
 
 typedef enum {
-  HAWKES_FP64 = 0,  /* every step in float64; exp from the device math library */
+  HAWKES_FP64 = 0,  /* every step in float64; the pair terms' exp by a table-driven
+                       method (Tang, 2^8 entries) good to a few ulp, the other
+                       special functions from the device math library */
   HAWKES_MIXED = 1, /* pair arithmetic and exp in float32, all sums, logs, the
                        compensator and final reductions in float64 */
   HAWKES_CULL = 0x10 /* flag, OR-ed into either precision: skip the column tiles
