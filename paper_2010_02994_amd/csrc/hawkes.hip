@@ -524,16 +524,18 @@ int run_sync(const double* x, const double* t, int64_t n, int d, const hawkes_pa
     for (int q = 0; q < 8; ++q) pin.host[q] = NAN;   // a status the kernel did not write reads as a device error
   int st = run_async(x, t, n, d, p, prec, ws, ws_bytes, stream, out8, grad_x, terms, pin.dev);
   if (st != HAWKES_OK) {
-    if (pin.host) pinned_pool().give(pin);
+    // argument errors come before any launch; after a failed launch some of
+    // the call's kernels may be queued, so the buffer is not reused
+    if (pin.host && st != HAWKES_EDEVICE) pinned_pool().give(pin);
     return st;
   }
   double h[8];
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (pin.host) {
-    const bool ok = hipStreamSynchronize(s) == hipSuccess;
+    if (hipStreamSynchronize(s) != hipSuccess) return HAWKES_EDEVICE;   // buffer not reused either
     for (int q = 0; q < 8; ++q) h[q] = static_cast<volatile double*>(pin.host)[q];
     pinned_pool().give(pin);
-    if (!ok || std::isnan(h[7])) return HAWKES_EDEVICE;
+    if (std::isnan(h[7])) return HAWKES_EDEVICE;
   } else {
     if (hipMemcpyAsync(h, out8, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return HAWKES_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return HAWKES_EDEVICE;
