@@ -184,6 +184,31 @@ def main():
             acc += np.array(stage[:])
         return el / steps, acc / max(stage_steps, 1), ll.value
 
+    # the same evaluations enqueued back to back with hawkes_grad_async (results
+    # stay on the device, one synchronization at the end), beside the headline's
+    # synchronous calls: the difference is the per-call host round trip.  Timed
+    # first, so that the headline's stage-timed calls stay the process's last
+    # dispatches of the mixed kernels
+    async_ms = None
+    if args.steps > 0:
+        ws_a = api.workspace(n, d, args.prec, dev)
+        out8 = torch.empty(8, dtype=torch.float64, device=dev)
+
+        def acall():
+            st = L.hawkes_grad_async(x.data_ptr(), t.data_ptr(), n, d, ctypes.byref(ps), api._prec(args.prec),
+                                     ws_a.data_ptr(), ws_a.numel(), stream, out8.data_ptr(), gx.data_ptr())
+            assert st == 0, _lib.strerror(st)
+
+        for _ in range(args.warmup):
+            acall()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            acall()
+        torch.cuda.synchronize()
+        async_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        assert out8[7].item() == 0.0
+
     step_stats = {}
     sec_mixed, stage_ms, ll_m = run(args.prec, args.steps, args.warmup, max(5, args.steps // 2), step_stats)
     pairs = n * (n - 1)
@@ -267,6 +292,8 @@ def main():
            "path_roofline_note": "both passes' algorithmic work (10D+39 FLOPs + 4 exps per unordered pair) over "
                                  "ms_per_step, against the same peak",
            "per_step": step_stats,
+           "async_back_to_back_ms_per_step": async_ms,
+           "async_note": "hawkes_grad_async calls enqueued back to back, one synchronization at the end",
            "stage_ms": {k: round(float(v), 4) for k, v in zip(STAGES, stage_ms)},
            "stage_ms_note": "stages timed in sequence on one stream (hawkes_grad_timed); ms_per_step is "
                             "hawkes_grad, where fix1, final1 and fix2 overlap pass2 on a side stream",
