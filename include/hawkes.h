@@ -152,7 +152,8 @@ int hawkes_diagnostics(const void* ws /* device */, size_t ws_bytes, int64_t n, 
  * HAWKES_NOALLOC_SCRATCH_BYTES per GPU (each GPU the library runs on holds
  * its own copy until the process ends), so the call allocates nothing and
  * creates no stream: the fix-up and finalize kernels share `stream` unless
- * a side stream is already pooled.  Limit: hawkes_workspace_bytes(n, d,
+ * a side stream is already pooled, and the scalars come back through a
+ * pooled pinned buffer only if one already exists (else by a copy).  Limit: hawkes_workspace_bytes(n, d,
  * prec) <= HAWKES_NOALLOC_SCRATCH_BYTES (about n <= 18,000 at d = 2), else
  * HAWKES_ENOMEM and nothing runs.  Every call on one GPU shares its array,
  * which keeps the last call's contents (each call writes every part it
