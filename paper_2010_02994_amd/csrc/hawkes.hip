@@ -296,8 +296,11 @@ class ForkPool {
     if (!allow_create) return nullptr;
     Fork f{};
     const bool s_ok = hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) == hipSuccess;
-    const bool r_ok = s_ok && hipEventCreateWithFlags(&f.ready, hipEventDisableTiming) == hipSuccess;
-    const bool d_ok = r_ok && hipEventCreateWithFlags(&f.done, hipEventDisableTiming) == hipSuccess;
+    // the two events only order the streams on the device (nothing on the
+    // host waits for them), so they record without the system-scope fence
+    constexpr unsigned kFlags = hipEventDisableTiming | hipEventDisableSystemFence;
+    const bool r_ok = s_ok && hipEventCreateWithFlags(&f.ready, kFlags) == hipSuccess;
+    const bool d_ok = r_ok && hipEventCreateWithFlags(&f.done, kFlags) == hipSuccess;
     if (!d_ok) {   // caller falls back to one stream
       if (r_ok) (void)hipEventDestroy(f.ready);
       if (s_ok) (void)hipStreamDestroy(f.side);
